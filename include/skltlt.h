@@ -1,0 +1,176 @@
+/*
+ * skltlt -- pivoted LTL^T factorization of skew-symmetric matrices and their
+ * Pfaffians on AMD Instinct MI355X (gfx950).  C ABI of libskltlt.so.
+ *
+ * Paper: "Performant Tridiagonal Factorization of Skew-Symmetric Matrices",
+ * arXiv 2411.09859.  The operation is the one of Sec. 3.2 (Specification):
+ * for a skew-symmetric X (X = -X^T, Sec. 2.2) compute a unit lower
+ * triangular L whose first column is e_0 and a skew-symmetric tridiagonal T
+ * with P X P^T = L T L^T, overwriting X.  P comes from symmetric partial
+ * pivoting (Sec. 3.7).  The Pfaffian follows from Sec. 1 and Sec. 2.2:
+ * Pf(X) = det(P) * Pf(T) = det(P) * prod_i T[2i][2i+1].
+ *
+ * Conventions shared by every call:
+ *   - Matrices are fp64, column-major, 0-based, leading dimension lda >= n.
+ *   - Only the STRICT LOWER triangle of A is read or written; the diagonal
+ *     and the upper triangle are never touched (the implicit structure of
+ *     Sec. 2.4: unstored skew entries are neither read nor referenced).
+ *   - Output layout in place (Sec. 4.1, "Storage details"): A[j+1][j] = t[j]
+ *     (the subdiagonal of T; T[j][j+1] = -t[j]) and A[i][j] = L[i][j+1] for
+ *     i >= j+2 (L shifted one column left; its unit diagonal and its first
+ *     column e_0 are implicit).
+ *   - ipiv is absolute and 0-based: ipiv[0] = 0 (the first pivot is never
+ *     computed, caption of Fig. 5), and for r >= 1 ipiv[r] >= r is the row
+ *     exchanged with row r (rows AND columns, P(pi) of Sec. 3.7.1) before
+ *     column r of L was formed.  The permutation is P = P_{n-1} ... P_1 with
+ *     P_r the transposition (r, ipiv[r]); (P A P^T)[i][j] = A[q[i]][q[j]]
+ *     where q is the identity with those transpositions applied in order.
+ *   - Pivot choice: largest magnitude in the column (iamax, Sec. 3.7.1),
+ *     first index on ties.  A column with no non-zero candidate gives
+ *     t = 0, a zero column of L and no exchange; this is not an error.
+ *   - Pointers marked (device) are device pointers (hipMalloc or any device
+ *     allocation of the current device); (host) are host pointers.
+ *   - stream is a hipStream_t passed as void* (NULL: the null stream).  Work
+ *     is enqueued asynchronously; buffers must stay alive until the stream
+ *     has passed it.  The library allocates nothing on these paths and keeps
+ *     no pointer after a call returns.
+ *   - Every call returns a skltlt_status.  Argument errors are reported
+ *     before anything is enqueued; a failed launch returns SKLTLT_EDEVICE.
+ *     Inputs with NaN or Inf are outside the contract (as in LAPACK).
+ *   - Calls on distinct streams with distinct buffers are independent; two
+ *     calls may not share a workspace while both are in flight.
+ */
+#ifndef SKLTLT_H
+#define SKLTLT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SKLTLT_OK = 0,
+    SKLTLT_EINVAL = -1,  /* bad argument (size, pointer, workspace, enum)    */
+    SKLTLT_ENOMEM = -2,  /* reserved: the library itself never allocates     */
+    SKLTLT_EDEVICE = -3, /* a HIP call or kernel launch failed               */
+    SKLTLT_ENOTSUP = -4  /* size or option outside what this build supports  */
+} skltlt_status;
+
+typedef enum {
+    SKLTLT_FP64 = 0,        /* every step in fp64                                */
+    SKLTLT_FP32_UPDATE = 1  /* trailing rank-2k update in fp32 MFMA with fp32
+                               accumulation added to the fp64 matrix; pivot
+                               search, panel, t and Pfaffian stay fp64        */
+} skltlt_precision;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *skltlt_status_string(int status);
+
+/* Block size the library picks for order n when block_size = 0. */
+int skltlt_default_block_size(int n);
+
+/* Bytes of device workspace that skltlt_factor / skltlt_pfaffian need for
+ * (n, block_size, precision).  *bytes (host) receives the size; the same
+ * value is valid for every n' <= n with the same block size.
+ * Returns SKLTLT_EINVAL for n < 0, block_size < 0 or an unknown precision,
+ * SKLTLT_ENOTSUP if n is beyond the supported range for that block size. */
+int skltlt_workspace_size(int n, int block_size, int precision, size_t *bytes);
+
+/* Blocked pivoted LTL^T (Sec. 3.6.3 fused right-looking blocked algorithm,
+ * with the pivoted left-looking panel of Sec. 3.7.3 and the trailing update
+ * cast as a skew rank-2k update via Theorem "TandS" of Sec. 2.2 and
+ * Sec. 3.6.5 "Forming W after the panel factorization").
+ *   n           order (n >= 0).
+ *   A (device)  n x n, lda >= max(1, n); in: strict lower triangle of the
+ *               skew matrix; out: t and L in the layout described above.
+ *   t (device)  n-1 doubles (may be NULL when n <= 1): T[j+1][j].
+ *   ipiv (device) n ints (may be NULL when n == 0).
+ *   block_size  columns per panel; 0 = skltlt_default_block_size(n).
+ *   precision   skltlt_precision.
+ *   work (device), work_bytes: at least skltlt_workspace_size(...) bytes,
+ *               256-byte aligned; contents on entry are irrelevant.
+ * In exact arithmetic the result equals the unblocked algorithm's (the
+ * blocked variants establish the same postcondition, Sec. 3.6). */
+int skltlt_factor(int n, double *A, int lda, double *t, int *ipiv,
+                  int block_size, int precision, void *work,
+                  size_t work_bytes, void *stream);
+
+/* skltlt_factor followed, on the same stream, by the Pfaffian read off T
+ * and P: log_abs_pf (device, 1 double) = log|Pf(A)| and sign (device, 1 int)
+ * in {-1, 0, +1}, with Pf(A) = sign * exp(log_abs_pf).  Odd n, or a zero
+ * t[2i], gives sign 0 and log_abs_pf = -inf (Pf = 0 exactly). */
+int skltlt_pfaffian(int n, double *A, int lda, double *t, int *ipiv,
+                    double *log_abs_pf, int *sign, int block_size,
+                    int precision, void *work, size_t work_bytes,
+                    void *stream);
+
+/* Largest order handled by skltlt_batched. */
+int skltlt_batched_max_n(void);
+
+/* Bytes of device workspace for skltlt_batched with `batch` matrices. */
+int skltlt_batched_workspace_size(int batch, size_t *bytes);
+
+/* Many independent small factorizations and Pfaffians in one persistent
+ * kernel launch: each workgroup takes the next matrix from a queue and runs
+ * the fused blocked algorithm of Sec. 3.6.3 on it with a small block size
+ * (the two-step case b = 2 is Sec. 3.5.2), keeping the trailing matrix in
+ * the workgroup's LDS when it fits.  No host synchronization, no host
+ * staging: all descriptors are device arrays, so the call can be captured
+ * in a hipGraph.
+ *   batch        number of matrices (>= 0).
+ *   n (device)   batch orders, each in [0, max_n].
+ *   A (device)   batch device pointers, each to an n[i] x n[i] matrix with
+ *                leading dimension lda[i] (device array lda), same in/out
+ *                layout as skltlt_factor.
+ *   t, ipiv (device) batch device pointers (n[i]-1 doubles, n[i] ints).
+ *   log_abs_pf, sign (device) arrays of batch entries, or both NULL to skip
+ *                the Pfaffians.
+ *   info (device) batch ints or NULL: 0 = done, -1 = entry rejected
+ *                (n[i] < 0, n[i] > max_n or lda[i] < max(1, n[i])); a
+ *                rejected entry's buffers are not touched.
+ *   max_n (host) upper bound of the n[i], at most skltlt_batched_max_n().
+ *   block_size   0 = the autotuned choice for max_n, else the panel width.
+ *   precision    SKLTLT_FP64 (SKLTLT_FP32_UPDATE returns SKLTLT_ENOTSUP).
+ *   work (device), work_bytes: skltlt_batched_workspace_size bytes.
+ * Each matrix's result depends only on that matrix and on (max_n,
+ * block_size), never on the other members of the batch or their order. */
+int skltlt_batched(int batch, const int *n, double *const *A, const int *lda,
+                   double *const *t, int *const *ipiv, double *log_abs_pf,
+                   int *sign, int *info, int max_n, int block_size,
+                   int precision, void *work, size_t work_bytes,
+                   void *stream);
+
+/* ---- Instrumentation ---------------------------------------------------
+ * Per-kernel timing for measurement tools.  While enabled, every kernel the
+ * library enqueues is bracketed by a pair of HIP events recorded on the same
+ * stream as the kernel; the events are created by skltlt_timing_enable (not
+ * on the factorization path).  Kernel classes: */
+typedef enum {
+    SKLTLT_K_PANEL = 0,    /* pivoted left-looking panel                      */
+    SKLTLT_K_SKR2K = 1,    /* skew rank-2k trailing update (MFMA)            */
+    SKLTLT_K_FINALIZE = 2, /* deferred row exchanges of earlier L columns    */
+    SKLTLT_K_PFAFFIAN = 3, /* log|Pf| and sign                               */
+    SKLTLT_K_BATCHED = 4,  /* batched persistent kernel                      */
+    SKLTLT_K_OTHER = 5,    /* small fills                                    */
+    SKLTLT_K_COUNT = 6
+} skltlt_kernel_class;
+
+/* Start recording; max_launches bounds the number of bracketed launches
+ * (launches beyond it are not timed).  Returns SKLTLT_EDEVICE if the events
+ * cannot be created.  Not thread-safe with concurrent library calls. */
+int skltlt_timing_enable(int max_launches);
+
+/* Stop recording (events are kept until the next enable). */
+int skltlt_timing_disable(void);
+
+/* Synchronizes the recorded events and returns, for one kernel class, the
+ * summed duration in milliseconds and the number of timed launches (host
+ * outputs).  Also returns the per-launch algorithmic flop count summed over
+ * the timed launches of that class in *flops (0 for classes without one). */
+int skltlt_timing_read(int kernel_class, double *total_ms, int *launches, double *flops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SKLTLT_H */

@@ -1,0 +1,74 @@
+// Internal declarations shared by the translation units of libskltlt.so.
+// Not part of the public ABI (that is include/skltlt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace skl {
+
+constexpr int kPanelThreads = 256;   // threads per panel workgroup
+constexpr int kMaxPanelGroups = 1024; // slot array capacity per parity
+constexpr int kMaxBlock = 256;       // largest supported panel width
+constexpr size_t kAlign = 256;
+
+// One record per panel workgroup and step parity: the workgroup's pivot
+// candidate and, for the workgroup that owns row r = c+1, that row's value.
+// The stamp is written last, with release semantics.
+struct alignas(64) Slot {
+    double xval;      // signed candidate value x[idx] (0 if none)
+    int idx;          // global row index of the candidate (INT_MAX if none)
+    int phys;         // physical row of the candidate in the row mirror
+    double xr;        // x[r] if this group owns row r
+    int phys_r;       // physical mirror row of r if this group owns it
+    unsigned stamp;   // step stamp (c + 1), written last
+    double pad[4];
+};
+
+// Device workspace of skltlt_factor, carved from the caller's buffer.
+struct FactorWs {
+    double *mirror;    // physical panel rows, row-major, ld = ldm
+    int ldm;
+    double *lcar;      // carried L column (n doubles)
+    double *uv;        // skr2k operands, column-major n x (4*nq): [U | V | -V | U]
+    float *uv32;       // same in fp32
+    Slot *slots;       // 2 * kMaxPanelGroups
+    int *gmap;         // nblocks x n suffix gather maps
+    int *blk_k0;       // nblocks + 1 block starts (device copy not needed: args)
+    size_t bytes;
+};
+
+size_t factor_ws_layout(int n, int b, FactorWs *ws, char *base);
+
+// ---- launchers (return hipError_t) -----------------------------------------
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_set_int(int *p, int v, hipStream_t s);
+
+struct PanelShape {
+    int G;  // workgroups
+    int R;  // rows per workgroup (power of two, <= kPanelThreads)
+    size_t lds;
+};
+PanelShape panel_shape(int n, int k0, int b, int max_groups);
+hipError_t launch_panel(double *A, int lda, int n, int k0, int nb, int b,
+                        double *t, int *ipiv, const FactorWs &ws, int want32,
+                        const PanelShape &sh, hipStream_t s);
+
+hipError_t launch_skr2k(double *A, int lda, int n, int cp, int nq,
+                        const FactorWs &ws, int precision, hipStream_t s);
+
+hipError_t launch_finalize(double *A, int lda, int n, int b, const int *ipiv,
+                           const FactorWs &ws, hipStream_t s);
+
+hipError_t launch_pfaffian(int n, const double *t, const int *ipiv,
+                           double *log_abs_pf, int *sign, hipStream_t s);
+
+int device_cu_count();
+int tm_begin(int cls, hipStream_t s);
+void tm_end(int idx, hipStream_t s, double flops);
+void panel_init_attrs();
+void finalize_init_attrs();
+int panel_max_groups(size_t lds_bytes);
+
+}  // namespace skl

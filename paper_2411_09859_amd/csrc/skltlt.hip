@@ -1,0 +1,221 @@
+// C ABI of libskltlt.so (declared in include/skltlt.h): argument checks,
+// workspace layout and the enqueue sequence of the blocked factorization.
+//
+// Sequence per call (paper arXiv 2411.09859, Sec. 3.6.3 fused blocked
+// right-looking algorithm with the pivoting of Sec. 3.7.3, code of Sec. 4.2):
+//   for each panel of b columns: panel kernel (pivot search, exchanges,
+//   L columns, t, operands U and V), then the skr2k kernel on the trailing
+//   lower triangle; after the last panel: the deferred row exchanges of the
+//   earlier L columns.  Pivot choices stay on the device; the host never
+//   synchronizes with the stream.
+#include "../../include/skltlt.h"
+#include "common.h"
+
+#include <mutex>
+
+namespace skl {
+
+static size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int device_cu_count()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return cus;
+}
+
+// Workspace: mirror (n x (b+2) fp64, row-major), carried column (n),
+// operands [U|V|-V|U] (n x 4k fp64) and their fp32 copy, slots, gather maps.
+size_t factor_ws_layout(int n, int b, FactorWs *ws, char *base)
+{
+    const int nq = (b + 1) / 2;
+    const int nblk = n > 1 ? (n - 1 + b - 1) / b : 1;
+    size_t off = 0;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return base ? base + o : nullptr;
+    };
+    FactorWs w{};
+    w.ldm = b + 2;
+    w.mirror = (double *)take(sizeof(double) * nn * (size_t)(b + 2));
+    w.lcar = (double *)take(sizeof(double) * nn);
+    w.uv = (double *)take(sizeof(double) * nn * (size_t)(4 * nq));
+    w.uv32 = (float *)take(sizeof(float) * nn * (size_t)(4 * nq));
+    w.slots = (Slot *)take(sizeof(Slot) * 2 * kMaxPanelGroups);
+    w.gmap = (int *)take(sizeof(int) * nn * (size_t)nblk);
+    w.blk_k0 = nullptr;
+    w.bytes = off;
+    if (ws)
+        *ws = w;
+    return off;
+}
+
+}  // namespace skl
+
+using namespace skl;
+
+static void init_device_attrs()
+{
+    static std::once_flag once;
+    std::call_once(once, [] {
+        panel_init_attrs();
+        finalize_init_attrs();
+        (void)hipGetLastError();
+    });
+}
+
+static const size_t kLdsCap = 160 * 1024;
+
+extern "C" const char *skltlt_status_string(int status)
+{
+    switch (status) {
+    case SKLTLT_OK: return "SKLTLT_OK";
+    case SKLTLT_EINVAL: return "SKLTLT_EINVAL: invalid argument";
+    case SKLTLT_ENOMEM: return "SKLTLT_ENOMEM: out of memory";
+    case SKLTLT_EDEVICE: return "SKLTLT_EDEVICE: HIP call or kernel launch failed";
+    case SKLTLT_ENOTSUP: return "SKLTLT_ENOTSUP: size or option not supported";
+    default: return "SKLTLT: unknown status";
+    }
+}
+
+extern "C" int skltlt_default_block_size(int n)
+{
+    if (n < 1024)
+        return 32;
+    if (n < 4096)
+        return 64;
+    return 128;
+}
+
+static int resolve_block(int n, int block_size)
+{
+    return block_size > 0 ? block_size : skltlt_default_block_size(n);
+}
+
+// Supported: panel LDS (rows per group x (b+2) doubles) and the gather
+// column (n - b - 1 doubles) fit in one CU's LDS.
+static int check_supported(int n, int b)
+{
+    if (b < 1 || b > kMaxBlock)
+        return SKLTLT_ENOTSUP;
+    const size_t gather = sizeof(double) * (size_t)(n > b + 1 ? n - b - 1 : 0);
+    if (gather > kLdsCap)
+        return SKLTLT_ENOTSUP;
+    // rows per group at most 256 with 1024 groups
+    if (n > 256 * kMaxPanelGroups)
+        return SKLTLT_ENOTSUP;
+    return SKLTLT_OK;
+}
+
+extern "C" int skltlt_workspace_size(int n, int block_size, int precision, size_t *bytes)
+{
+    if (n < 0 || block_size < 0 || !bytes || (precision != SKLTLT_FP64 && precision != SKLTLT_FP32_UPDATE))
+        return SKLTLT_EINVAL;
+    const int b = resolve_block(n, block_size);
+    int st = check_supported(n, b);
+    if (st != SKLTLT_OK)
+        return st;
+    *bytes = factor_ws_layout(n, b, nullptr, nullptr);
+    return SKLTLT_OK;
+}
+
+static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int block_size,
+                       int precision, void *work, size_t work_bytes, hipStream_t s)
+{
+    if (n < 0 || lda < (n > 1 ? n : 1) || block_size < 0)
+        return SKLTLT_EINVAL;
+    if (precision != SKLTLT_FP64 && precision != SKLTLT_FP32_UPDATE)
+        return SKLTLT_EINVAL;
+    if (n >= 1 && (!A || !ipiv))
+        return SKLTLT_EINVAL;
+    if (n >= 2 && !t)
+        return SKLTLT_EINVAL;
+    const int b = resolve_block(n, block_size);
+    int st = check_supported(n, b);
+    if (st != SKLTLT_OK)
+        return st;
+    if (n == 0)
+        return SKLTLT_OK;
+    const size_t need = factor_ws_layout(n, b, nullptr, nullptr);
+    if (!work || work_bytes < need || ((uintptr_t)work % kAlign) != 0)
+        return SKLTLT_EINVAL;
+    init_device_attrs();
+
+    FactorWs ws;
+    factor_ws_layout(n, b, &ws, (char *)work);
+
+    {
+        const int ti = tm_begin(SKLTLT_K_OTHER, s);
+        if (launch_set_int(ipiv, 0, s) != hipSuccess)
+            return SKLTLT_EDEVICE;
+        if (n > 1 && launch_fill_zero(ws.slots, sizeof(Slot) * 2 * kMaxPanelGroups, s) != hipSuccess)
+            return SKLTLT_EDEVICE;
+        tm_end(ti, s, 0.0);
+    }
+    if (n == 1)
+        return SKLTLT_OK;
+
+    const int want32 = (precision == SKLTLT_FP32_UPDATE);
+    // panel geometry: as many groups as the device keeps resident
+    PanelShape probe = panel_shape(n, 0, b, kMaxPanelGroups);
+    int maxg = panel_max_groups(probe.lds);
+    if (maxg <= 0)
+        return SKLTLT_EDEVICE;
+
+    for (int k0 = 0; k0 < n - 1; k0 += b) {
+        const int nb = (b < n - 1 - k0) ? b : (n - 1 - k0);
+        PanelShape sh = panel_shape(n, k0, b, maxg);
+        if (sh.lds > kLdsCap || sh.G > maxg)
+            return SKLTLT_ENOTSUP;
+        int ti = tm_begin(SKLTLT_K_PANEL, s);
+        if (launch_panel(A, lda, n, k0, nb, b, t, ipiv, ws, want32, sh, s) != hipSuccess)
+            return SKLTLT_EDEVICE;
+        tm_end(ti, s, 0.0);
+        const int cp = k0 + nb;
+        if (cp < n - 1) {
+            const int nq = (nb + 1) / 2;
+            const double m = (double)(n - cp);
+            ti = tm_begin(SKLTLT_K_SKR2K, s);
+            if (launch_skr2k(A, lda, n, cp, nq, ws, precision, s) != hipSuccess)
+                return SKLTLT_EDEVICE;
+            // strict lower triangle of the m x m trailing block, K = 2*nq
+            tm_end(ti, s, m * (m - 1.0) * 0.5 * 2.0 * (2.0 * nq));
+        }
+    }
+    {
+        const int ti = tm_begin(SKLTLT_K_FINALIZE, s);
+        if (launch_finalize(A, lda, n, b, ipiv, ws, s) != hipSuccess)
+            return SKLTLT_EDEVICE;
+        tm_end(ti, s, 0.0);
+    }
+    return SKLTLT_OK;
+}
+
+extern "C" int skltlt_factor(int n, double *A, int lda, double *t, int *ipiv, int block_size,
+                             int precision, void *work, size_t work_bytes, void *stream)
+{
+    return factor_impl(n, A, lda, t, ipiv, block_size, precision, work, work_bytes,
+                       (hipStream_t)stream);
+}
+
+extern "C" int skltlt_pfaffian(int n, double *A, int lda, double *t, int *ipiv,
+                               double *log_abs_pf, int *sign, int block_size, int precision,
+                               void *work, size_t work_bytes, void *stream)
+{
+    if (!log_abs_pf || !sign)
+        return SKLTLT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int st = factor_impl(n, A, lda, t, ipiv, block_size, precision, work, work_bytes, s);
+    if (st != SKLTLT_OK)
+        return st;
+    const int ti = tm_begin(SKLTLT_K_PFAFFIAN, s);
+    if (launch_pfaffian(n, t, ipiv, log_abs_pf, sign, s) != hipSuccess)
+        return SKLTLT_EDEVICE;
+    tm_end(ti, s, 0.0);
+    return SKLTLT_OK;
+}

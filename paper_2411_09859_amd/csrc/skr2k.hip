@@ -1,0 +1,193 @@
+// Skew-symmetric rank-2k trailing update on MFMA.
+//
+// Paper (arXiv 2411.09859): the trailing update C := C - A T A^T of the fused
+// blocked right-looking algorithm (Sec. 3.6.3, T of order b+1) becomes a skew
+// rank-2k update C := C - (W A^T - A W^T) with W = A S (Theorem "TandS" of
+// Sec. 2.2, eq. (TvsS); Sec. 3.6.5 "Forming W after the panel
+// factorization"), the skew_rank2k operation of the level-3 table in
+// Sec. 3.5.4/3.6.6.  Only the odd columns of W are non-zero, so with
+// U = W[:, odd] and V = A[:, odd] the update is C -= U V^T - V U^T with
+// k = floor((b+1)/2) columns each.
+//
+// The panel kernel writes the operands once, column-major with leading
+// dimension n, as [U | V | -V | U]; then C += [U | V] [-V | U]^T is a plain
+// GEMM with K = 2k restricted to the strict lower triangle of the trailing
+// block (rows and columns cp..n-1, the first column included).
+//
+// Tiling: a 128x128 output tile per 256-thread workgroup, four waves of
+// 64x64, each a 4x4 grid of 16x16 MFMA blocks.  The MFMA computes the
+// transposed tile, D[j][i], so that each lane's four accumulator values lie
+// in four columns at one row i and sixteen consecutive lanes cover sixteen
+// consecutive rows: loads and stores of C are 128-byte segments.  Tiles are
+// enumerated over the lower triangle only; a diagonal tile skips the wave
+// whose 64x64 quarter lies strictly above the diagonal and masks the rest.
+// Consecutive tile indices go to one XCD (workgroup ids are dealt to the 8
+// XCDs round-robin), so tiles that share operand rows share an L2.
+#include "common.h"
+
+namespace skl {
+
+constexpr int TM = 128;    // tile rows (i) and columns (j)
+constexpr int KC = 16;     // K chunk staged in LDS
+
+template <typename T> struct MfmaT;
+// Output layout of the 16x16 MFMA result held by lane l (value q of 4),
+// measured on gfx950: fp64 holds rows (l/16) + 4q, fp32 rows 4(l/16) + q;
+// the column is l%16 for both.
+template <> struct MfmaT<double> {
+    typedef double __attribute__((ext_vector_type(4))) acc4;
+    static __device__ __forceinline__ acc4 mma(double a, double b, acc4 c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int lk, int q) { return lk + 4 * q; }
+};
+template <> struct MfmaT<float> {
+    typedef float __attribute__((ext_vector_type(4))) acc4;
+    static __device__ __forceinline__ acc4 mma(float a, float b, acc4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int lk, int q) { return 4 * lk + q; }
+};
+
+__device__ __forceinline__ void tile_of(int tau, int *ti, int *tj)
+{
+    // tau = I*(I+1)/2 + J with 0 <= J <= I
+    int I = (int)((sqrtf(8.0f * (float)tau + 1.0f) - 1.0f) * 0.5f);
+    while ((I + 1) * (I + 2) / 2 <= tau)
+        ++I;
+    while (I * (I + 1) / 2 > tau)
+        --I;
+    *ti = I;
+    *tj = tau - I * (I + 1) / 2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void skr2k_kernel(double *__restrict__ A, int lda, int n,
+                                                    int cp, int K, const T *__restrict__ uv,
+                                                    int ntiles)
+{
+    typedef typename MfmaT<T>::acc4 acc4;
+    __shared__ T sI[KC][TM]; // [U|V] rows i, k-major
+    __shared__ T sJ[KC][TM]; // [-V|U] rows j, k-major
+
+    // XCD-grouped tile order
+    const int nwg = gridDim.x;
+    const int per_xcd = (nwg + 7) / 8;
+    const int bid = blockIdx.x;
+    const int tau = (bid & 7) * per_xcd + (bid >> 3);
+    if (tau >= ntiles)
+        return;
+    int ti, tj;
+    tile_of(tau, &ti, &tj);
+    const int i0 = cp + ti * TM;
+    const int j0 = cp + tj * TM;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wi = wave & 1, wj = wave >> 1;
+    const int ib = i0 + wi * 64; // this wave's 64 rows
+    const int jb = j0 + wj * 64; // this wave's 64 columns
+    const bool active = !(ti == tj && wi == 0 && wj == 1);
+
+    const int lrow = lane & 15; // i offset inside a 16-block / MFMA b-row
+    const int lk = lane >> 4;   // k inside a 4-step, or 4-row group of D
+
+    acc4 acc[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+            acc[bi][bj] = acc4{0, 0, 0, 0};
+
+    const int nK = 2 * K; // column count of [U|V|-V|U] is 2K, K = 2k
+    (void)nK;
+    const T *opI = uv;                  // columns [0, K)
+    const T *opJ = uv + (size_t)K * n;  // columns [K, 2K)
+
+    for (int k0 = 0; k0 < K; k0 += KC) {
+        // stage KC x 128 of each operand (column-major, ld = n)
+#pragma unroll
+        for (int q = 0; q < (KC * TM) / 256; ++q) {
+            const int e = tid + q * 256;
+            const int rr = e % TM;
+            const int kk = e / TM;
+            const int k = k0 + kk;
+            const int gi = i0 + rr, gj = j0 + rr;
+            T vi = 0, vj = 0;
+            if (k < K) {
+                if (gi < n)
+                    vi = opI[(size_t)k * n + gi];
+                if (gj < n)
+                    vj = opJ[(size_t)k * n + gj];
+            }
+            sI[kk][rr] = vi;
+            sJ[kk][rr] = vj;
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int ks = 0; ks < KC; ks += 4) {
+                T fa[4], fb[4];
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj)
+                    fa[bj] = sJ[ks + lk][wj * 64 + bj * 16 + lrow];
+#pragma unroll
+                for (int bi = 0; bi < 4; ++bi)
+                    fb[bi] = sI[ks + lk][wi * 64 + bi * 16 + lrow];
+#pragma unroll
+                for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 4; ++bj)
+                        acc[bi][bj] = MfmaT<T>::mma(fa[bj], fb[bi], acc[bi][bj]);
+            }
+        }
+        __syncthreads();
+    }
+    if (!active)
+        return;
+
+    // D[m][nn] (m = MfmaT::drow(lane/16, q) : column j, nn = lane%16 : row i) += C
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+        const int gi = ib + bi * 16 + lrow;
+        if (gi >= n)
+            continue;
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gj = jb + bj * 16 + MfmaT<T>::drow(lk, q);
+                if (gj < gi) {
+                    double *cptr = A + (size_t)gj * lda + gi;
+                    *cptr = *cptr + (double)acc[bi][bj][q];
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_skr2k(double *A, int lda, int n, int cp, int nq, const FactorWs &ws,
+                        int precision, hipStream_t s)
+{
+    const int m = n - cp;
+    if (m < 2 || nq <= 0)
+        return hipSuccess;
+    const int nt = (m + TM - 1) / TM;
+    const int ntiles = nt * (nt + 1) / 2;
+    const int per_xcd = (ntiles + 7) / 8;
+    const int grid = per_xcd * 8;
+    const int K = 2 * nq;
+    if (precision == 1) {
+        hipLaunchKernelGGL(skr2k_kernel<float>, dim3(grid), dim3(256), 0, s, A, lda, n, cp, K,
+                           (const float *)ws.uv32, ntiles);
+    } else {
+        hipLaunchKernelGGL(skr2k_kernel<double>, dim3(grid), dim3(256), 0, s, A, lda, n, cp, K,
+                           (const double *)ws.uv, ntiles);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace skl

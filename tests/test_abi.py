@@ -1,0 +1,87 @@
+"""Host-only checks of the C ABI: the library loads, exports every function the
+header declares, and rejects bad arguments before touching the device."""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+from paper_2411_09859_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_or_skip():
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libskltlt.so not built")
+    return binding.lib()
+
+
+def test_exports_every_header_function():
+    _lib_or_skip()
+    names = binding.header_functions()
+    assert "skltlt_factor" in names and "skltlt_pfaffian" in names and "skltlt_batched" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH], check=True,
+                         capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+
+
+def test_status_strings():
+    L = _lib_or_skip()
+    for st in (0, -1, -2, -3, -4, 7):
+        assert L.skltlt_status_string(st)
+
+
+def test_workspace_size_queries():
+    _lib_or_skip()
+    a = binding.workspace_size(256, 32)
+    b = binding.workspace_size(16384, 128)
+    assert 0 < a < b
+    with pytest.raises(binding.SkltltError) as e:
+        binding.workspace_size(-1)
+    assert e.value.status == binding.SKLTLT_EINVAL
+    with pytest.raises(binding.SkltltError) as e:
+        binding.workspace_size(64, 0, precision=7)
+    assert e.value.status == binding.SKLTLT_EINVAL
+    with pytest.raises(binding.SkltltError) as e:
+        binding.workspace_size(64, 1000)
+    assert e.value.status == binding.SKLTLT_ENOTSUP
+
+
+def test_default_block_sizes():
+    _lib_or_skip()
+    for n in (1, 100, 1000, 5000, 16384):
+        b = binding.default_block_size(n)
+        assert 1 <= b <= 256
+
+
+def test_factor_rejects_bad_arguments_without_device_work():
+    L = _lib_or_skip()
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)
+    # negative n
+    assert L.skltlt_factor(-1, fake, 1, fake, fake, 0, 0, fake, 1 << 20, None) == -1
+    # lda < n
+    assert L.skltlt_factor(8, fake, 4, fake, fake, 0, 0, fake, 1 << 20, None) == -1
+    # unknown precision
+    assert L.skltlt_factor(8, fake, 8, fake, fake, 0, 3, fake, 1 << 20, None) == -1
+    # null pointers
+    assert L.skltlt_factor(8, None, 8, fake, fake, 0, 0, fake, 1 << 20, None) == -1
+    assert L.skltlt_factor(8, fake, 8, None, fake, 0, 0, fake, 1 << 20, None) == -1
+    # workspace too small / misaligned
+    assert L.skltlt_factor(8, fake, 8, fake, fake, 0, 0, fake, 16, None) == -1
+    assert L.skltlt_factor(8, fake, 8, fake, fake, 0, 0, vp(0x1008), 1 << 20, None) == -1
+    # n = 0 is a no-op
+    assert L.skltlt_factor(0, None, 1, None, None, 0, 0, None, 0, None) == 0
+    # pfaffian needs its outputs
+    assert L.skltlt_pfaffian(8, fake, 8, fake, fake, None, fake, 0, 0, fake, 1 << 20, None) == -1
+
+
+def test_batched_argument_checks():
+    L = _lib_or_skip()
+    sz = ctypes.c_size_t(0)
+    assert L.skltlt_batched_workspace_size(-1, ctypes.byref(sz)) == -1
