@@ -8,22 +8,18 @@
 
 namespace skl {
 
-constexpr int kPanelThreads = 256;   // threads per panel workgroup
+constexpr int kPanelThreads = 512;   // threads per panel workgroup
 constexpr int kMaxPanelGroups = 1024; // slot array capacity per parity
 constexpr int kMaxBlock = 256;       // largest supported panel width
 constexpr size_t kAlign = 256;
 
-// One record per panel workgroup and step parity: the workgroup's pivot
-// candidate and, for the workgroup that owns row r = c+1, that row's value.
-// The stamp is written last, with release semantics.
+// One record per panel workgroup and step parity, as eight 8-byte words,
+// each with the 32-bit step stamp in its high half: [0,1] the candidate value
+// x[idx] (high and low halves of the double), [2] the candidate row index,
+// [3] its physical row in the row mirror; the group owning row r = c+1 also
+// writes [4,5] x[r] and [6] the physical row of r.
 struct alignas(64) Slot {
-    double xval;      // signed candidate value x[idx] (0 if none)
-    int idx;          // global row index of the candidate (INT_MAX if none)
-    int phys;         // physical row of the candidate in the row mirror
-    double xr;        // x[r] if this group owns row r
-    int phys_r;       // physical mirror row of r if this group owns it
-    unsigned stamp;   // step stamp (c + 1), written last
-    double pad[4];
+    unsigned long long w[8];
 };
 
 // Device workspace of skltlt_factor, carved from the caller's buffer.

@@ -9,30 +9,39 @@
 // Sec. 3.6.3); L and t are kept outside X while factoring and t is moved
 // onto the subdiagonal afterwards (Sec. 4.1).
 //
-// One cooperative launch handles one panel of nb column steps.  Workgroup w
-// owns the trailing rows k0+1+w*R .. k0+1+(w+1)*R-1 and keeps their panel
-// rows of L (the carried column and the nb new ones) in LDS.  Each column
-// step c (r = c+1):
-//   1. h = T_p * L[c, panel]^T from the previous pivot row (all groups
-//      compute it redundantly from the same data);
-//   2. x_i = Y[i, c] - L[i, panel] . h for owned rows i >= r (Y is the
-//      trailing matrix as of the panel start, with this panel's symmetric
-//      exchanges applied in place);
-//   3. local argmax of |x_i| (first index on ties), published in a slot
-//      whose stamp is stored last with release semantics;
-//   4. every group polls all stamps, then reduces the slots identically:
-//      pivot p, tau = x_p;
+// One cooperative launch handles one panel of nb column steps.  A workgroup
+// of 512 threads owns R = 512/TPR consecutive trailing rows; the TPR threads
+// of a row hold that row of the panel's L (the carried column and the nb new
+// ones, column a in thread a % TPR, register a / TPR) in registers, so a
+// group covers 256 rows at b = 128 and the whole n = 16384 trailing matrix
+// needs only 64 groups (the cost of the per-step exchange grows with the
+// number of groups).  Each column step c (r = c+1):
+//   1. h = T_p * L[c, panel]^T from the previous pivot row (computed
+//      redundantly by every group from the same data);
+//   2. x_i = Y[i, c] - L[i, panel] . h for owned rows i >= r, where Y is the
+//      trailing matrix as of the panel start with this panel's symmetric
+//      exchanges applied in place;
+//   3. argmax of |x_i| (first index on ties) over the group;
+//   4. with several groups: each group publishes its candidate in a slot of
+//      self-validating words (every 8-byte word carries the step stamp) and
+//      polls all slots; every group reduces them to the same pivot p;
 //   5. exchange rows/columns r <-> p of the trailing matrix (lower storage
-//      rule, one element per owned row), exchange the LDS rows r and p,
+//      rule, one element per row), relabel the register rows of r and p,
 //      and form the new column of L, l = x / tau (0 if tau = 0).
-// Panel rows are mirrored row-major in HBM under a physical-row indirection:
-// an exchange swaps the owners' physical indices instead of moving data, so
-// no mirror row that another group may still be reading is ever rewritten.
+// An exchange of rows r and p never moves register data: the two register
+// rows swap the matrix rows they stand for (the one that held r keeps its x
+// and continues as p; the one that held p is row r, final for this panel).
+// Other groups read the pivot row from a row-major mirror in HBM indexed by
+// register row, which is written once per column and never rewritten.
+// Cross-group words (slots, the mirror, the trailing matrix) are relaxed
+// device-scope atomics: coherent across XCDs without L2 write-back or
+// invalidation.
 #include "common.h"
 
 #include <climits>
 
 namespace skl {
+
 
 __device__ __forceinline__ bool beats(double av, int ai, double bv, int bi)
 {
@@ -40,49 +49,123 @@ __device__ __forceinline__ bool beats(double av, int ai, double bv, int bi)
     return (aa > bb) || (aa == bb && ai < bi);
 }
 
-__global__ __launch_bounds__(kPanelThreads) void panel_kernel(
+__device__ __forceinline__ double ld_dev(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_dev(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Stores read only by groups on the same XCD: a plain store is acknowledged
+// by the shared L2, and device-scope loads on that XCD observe it.
+__device__ __forceinline__ void st_xcd(double *p, double v, bool local)
+{
+    if (local)
+        *p = v;
+    else
+        st_dev(p, v);
+}
+__device__ __forceinline__ void st_xcd(unsigned long long *p, unsigned long long v, bool local)
+{
+    if (local)
+        *p = v;
+    else
+        st_dev(p, v);
+}
+// Wait until this wave's outstanding memory operations have completed.
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// A slot word: 32-bit step stamp in the high half, 32-bit payload below.
+__device__ __forceinline__ unsigned long long sw(unsigned stamp, unsigned payload)
+{
+    return ((unsigned long long)stamp << 32) | payload;
+}
+
+// bounded waits: a stuck peer never hangs the GPU (the result is poisoned)
+constexpr long kSpinLimit = 1L << 20;
+
+template <int NT, int TPR, int kNS>
+__global__ __launch_bounds__(NT) void panel_kernel(
     double *__restrict__ A, int lda, int n, int k0, int nb, int b,
     double *__restrict__ t, int *__restrict__ ipiv, double *__restrict__ mirror,
     int ldm, double *__restrict__ lcar, double *__restrict__ uv,
-    float *__restrict__ uv32, int want32, Slot *__restrict__ slots, int G, int R)
+    float *__restrict__ uv32, int want32, Slot *__restrict__ slots, int G, int one_xcd)
 {
-    extern __shared__ double smem[];
-    const int ldl = b + 2;
-    double *Lp = smem;                  // R x ldl
-    double *hrow = Lp + (size_t)R * ldl; // b+2: pivot row of the previous step
-    double *rrow = hrow + (b + 2);      // b+2: old row r (owner of p only)
-    double *hv = rrow + (b + 2);        // b+2: h
-    double *xl = hv + (b + 2);          // R
-    double *tl = xl + R;                // b
-    int *perm = (int *)(tl + b);        // R
+    constexpr int R = NT / TPR;
+    constexpr int NW = NT / 64;
+    constexpr int NA = kNS * TPR; // columns representable per row
+    extern __shared__ double stage[]; // R x 34, epilogue only
 
-    __shared__ double red_v[kPanelThreads / 64];
-    __shared__ int red_i[kPanelThreads / 64];
-    __shared__ int red_ph[kPanelThreads / 64];
-    __shared__ double bc_tau, bc_xr;
-    __shared__ int bc_p, bc_physp, bc_physr;
+    __shared__ double hv[NA];
+    __shared__ double hrow[NA];
+    __shared__ double tl[kMaxBlock];
+    __shared__ int pl[kMaxBlock];
+    __shared__ int posl[R];
+    __shared__ double red_v[NW];
+    __shared__ int red_i[NW], red_ph[NW];
+    __shared__ double bc_tau;
+    __shared__ int bc_p, bc_physp, bc_fail;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int w = blockIdx.x;
-    const int base = k0 + 1;          // first trailing row
-    const int row0 = base + w * R;    // first row owned by this group
-    const int TPR = kPanelThreads / R; // threads per row (power of two)
-    const int lr = tid / TPR;
-    const int sub = tid - lr * TPR;
-    const int myrow = row0 + lr;
-    const bool rowvalid = (lr < R) && (myrow < n);
-
-    // ---- panel start: carried column, physical indices, first column of Y
-    double ycol = 0.0;
-    if (rowvalid && sub == 0) {
-        const double l0 = (k0 == 0) ? 0.0 : lcar[myrow];
-        Lp[(size_t)lr * ldl] = l0;
-        perm[lr] = myrow - base;
-        mirror[(size_t)(myrow - base) * ldm] = l0;
-        ycol = A[(size_t)k0 * lda + myrow];
+    // With one_xcd the grid holds 8 workgroups per panel group and only those
+    // with an id divisible by 8 work: workgroup ids are dealt round-robin to
+    // the 8 XCDs, so all working groups share one XCD, which shortens the
+    // device-scope round trips of the exchange (correctness does not depend
+    // on the placement, every cross-group access is device-scope).
+    int w = blockIdx.x;
+    if (one_xcd) {
+        if (w & 7)
+            return;
+        w >>= 3;
     }
+    const int base = k0 + 1;        // first trailing row
+    const int lr = tid / TPR;       // register row of this thread
+    const int sub = tid - lr * TPR; // column class of this thread
+    const int phys = w * R + lr;    // its row in the mirror (fixed)
+    const bool multi = (G > 1);
+    const bool local = (one_xcd != 0);
+    unsigned long long *sl64 = (unsigned long long *)slots;
+
+    // The matrix row a register row represents.  Exchanging rows r and p
+    // relabels the two register rows instead of moving their data: the one
+    // that held row r now holds row p and keeps its x, the one that held
+    // row p becomes row r, which is final for this panel.
+    int pos = base + phys;
+    const bool exists = (pos < n);
+
+    double Lreg[kNS];
+#pragma unroll
+    for (int q = 0; q < kNS; ++q)
+        Lreg[q] = 0.0;
+
+    // ---- panel start: carried column (column 0 of the panel) and the first
+    //      column of Y
+    double ycol = 0.0;
+    for (int a = tid; a < NA; a += NT) {
+        hv[a] = 0.0;
+        hrow[a] = 0.0;
+    }
+    if (exists && sub == 0) {
+        const double l0 = (k0 == 0) ? 0.0 : lcar[pos];
+        Lreg[0] = l0;
+        if (multi)
+            st_xcd(&mirror[(size_t)phys * ldm], l0, local);
+        ycol = ld_dev(&A[(size_t)k0 * lda + pos]);
+    }
+    ycol = __shfl(ycol, lane & ~(TPR - 1), 64);
+    if (tid == 0)
+        bc_fail = 0;
     __syncthreads();
 
     for (int j = 0; j < nb; ++j) {
@@ -90,9 +173,11 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(
         const int r = c + 1;
         const int par = c & 1;
         const bool last = (r == k0 + nb);
+        const unsigned stamp = (unsigned)(c + 1);
 
         // 1. h[a] = sum_b T[a][b] L[c][b] over the panel columns a, b in 0..j,
         //    T tridiagonal with T[a+1][a] = t_a, T[a][a+1] = -t_a, L[c][j] = 1.
+        //    Entries of h beyond j stay zero.
         if (tid <= j) {
             const int a = tid;
             double v = 0.0;
@@ -104,31 +189,37 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(
         }
         __syncthreads();
 
-        // 2. x_i = Y[i, c] - sum_a L[i][a] h[a] for owned rows i >= r.
-        const bool cand = rowvalid && (myrow >= r);
-        double s = 0.0;
-        if (cand) {
-            const double *Lrow = Lp + (size_t)lr * ldl;
-            for (int a = sub; a <= j; a += TPR)
-                s += Lrow[a] * hv[a];
+        // 2. x_i = Y[i, c] - sum_a L[i][a] h[a] over the filled columns.
+        const bool cand = exists && (pos >= r);
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+        for (int q = 0; q < kNS; q += 4) {
+            if (q * TPR <= j) { // uniform: only the filled columns 0..j
+                s0 += Lreg[q] * hv[sub + TPR * q];
+                if (q + 1 < kNS)
+                    s1 += Lreg[q + 1] * hv[sub + TPR * (q + 1)];
+                if (q + 2 < kNS)
+                    s2 += Lreg[q + 2] * hv[sub + TPR * (q + 2)];
+                if (q + 3 < kNS)
+                    s3 += Lreg[q + 3] * hv[sub + TPR * (q + 3)];
+            }
         }
+        double s = (s0 + s1) + (s2 + s3);
+#pragma unroll
         for (int off = TPR >> 1; off >= 1; off >>= 1)
             s += __shfl_xor(s, off, 64);
-        double xv = 0.0;
-        if (cand && sub == 0) {
-            xv = ycol - s;
-            xl[lr] = xv;
-        }
+        const double xv = ycol - s;
 
-        // 3. local argmax: largest |x|, smallest row index on ties.
+        // 3. group argmax: largest |x|, smallest row index on ties.
         double cv = 0.0;
         int ci = INT_MAX, cph = 0;
         if (cand && sub == 0) {
             cv = xv;
-            ci = myrow;
-            cph = perm[lr];
+            ci = pos;
+            cph = phys;
         }
-        for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int off = 32; off >= TPR; off >>= 1) {
             const double ov = __shfl_xor(cv, off, 64);
             const int oi = __shfl_xor(ci, off, 64);
             const int oph = __shfl_xor(cph, off, 64);
@@ -143,70 +234,92 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(
             red_i[wave] = ci;
             red_ph[wave] = cph;
         }
+        // this wave's exchange and mirror stores of the previous step must be
+        // complete before this step's slot is published
+        if (multi)
+            wait_vm();
         __syncthreads();
 
-        const int wr = (r - base) / R; // group owning row r
         if (tid == 0) {
             double bv = red_v[0];
             int bi = red_i[0], bph = red_ph[0];
-            for (int q = 1; q < kPanelThreads / 64; ++q) {
+#pragma unroll
+            for (int q = 1; q < NW; ++q) {
                 if (beats(red_v[q], red_i[q], bv, bi)) {
                     bv = red_v[q];
                     bi = red_i[q];
                     bph = red_ph[q];
                 }
             }
-            Slot *sl = &slots[par * kMaxPanelGroups + w];
-            sl->xval = bv;
-            sl->idx = bi;
-            sl->phys = bph;
-            if (w == wr) {
-                const int lrr = (r - base) - w * R;
-                sl->xr = xl[lrr];
-                sl->phys_r = perm[lrr];
-            }
-            __hip_atomic_store(&sl->stamp, (unsigned)(c + 1), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        }
-
-        // 4. wait for every group's slot of this step.
-        if (wave == 0) {
-            for (int q = lane; q < G; q += 64) {
-                const Slot *s2 = &slots[par * kMaxPanelGroups + q];
-                while (__hip_atomic_load(&s2->stamp, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT) != (unsigned)(c + 1))
-                    __builtin_amdgcn_s_sleep(1);
+            if (multi) {
+                unsigned long long *wv =
+                    sl64 + (size_t)(par * kMaxPanelGroups + w) * (sizeof(Slot) / 8);
+                const unsigned long long xb = (unsigned long long)__double_as_longlong(bv);
+                const unsigned s16 = stamp & 0xffffu;
+                st_xcd(&wv[0], sw(stamp, (unsigned)(xb >> 32)), local);
+                st_xcd(&wv[1], sw(stamp, (unsigned)(xb & 0xffffffffu)), local);
+                // row relative to the panel base (0xffffff: none) and mirror
+                // row, 24 bits each, under a 16-bit stamp
+                const unsigned ib = (bi == INT_MAX) ? 0xffffffu : (unsigned)(bi - base);
+                st_xcd(&wv[2], ((unsigned long long)s16 << 48) |
+                                   ((unsigned long long)ib << 24) | (unsigned)bph, local);
+            } else {
+                bc_tau = bv;
+                bc_p = bi;
+                bc_physp = bph;
             }
         }
-        __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
-        // global winner, reduced identically in every group
-        {
+        // 4. several groups: poll all slots (one per thread) and reduce them
+        //    identically in every group.
+        if (multi) {
             double gv = 0.0;
             int gi = INT_MAX, gph = 0;
-            for (int q = tid; q < G; q += kPanelThreads) {
-                const Slot *s2 = &slots[par * kMaxPanelGroups + q];
-                const double v2 = s2->xval;
-                const int i2 = s2->idx;
+            const unsigned s16 = stamp & 0xffffu;
+            for (int q = tid; q < G; q += NT) {
+                const unsigned long long *wv =
+                    sl64 + (size_t)(par * kMaxPanelGroups + q) * (sizeof(Slot) / 8);
+                unsigned long long w0, w1, w2;
+                long spins = 0;
+                for (;;) {
+                    w0 = ld_dev(&wv[0]);
+                    w1 = ld_dev(&wv[1]);
+                    w2 = ld_dev(&wv[2]);
+                    if ((unsigned)(w0 >> 32) == stamp && (unsigned)(w1 >> 32) == stamp &&
+                        (unsigned)(w2 >> 48) == s16)
+                        break;
+                    if (bc_fail || ++spins > kSpinLimit) {
+                        bc_fail = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                const double v2 = __longlong_as_double(
+                    (long long)(((w0 & 0xffffffffull) << 32) | (w1 & 0xffffffffull)));
+                const unsigned ib = (unsigned)((w2 >> 24) & 0xffffffu);
+                const int i2 = (ib == 0xffffffu) ? INT_MAX : base + (int)ib;
                 if (beats(v2, i2, gv, gi)) {
                     gv = v2;
                     gi = i2;
-                    gph = s2->phys;
+                    gph = (int)(w2 & 0xffffffu);
                 }
             }
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double ov = __shfl_xor(gv, off, 64);
-                const int oi = __shfl_xor(gi, off, 64);
-                const int oph = __shfl_xor(gph, off, 64);
-                if (beats(ov, oi, gv, gi)) {
-                    gv = ov;
-                    gi = oi;
-                    gph = oph;
+            // reduce the candidates held by the waves that polled
+            if (wave * 64 < G) {
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const double ov = __shfl_xor(gv, off, 64);
+                    const int oi = __shfl_xor(gi, off, 64);
+                    const int oph = __shfl_xor(gph, off, 64);
+                    if (beats(ov, oi, gv, gi)) {
+                        gv = ov;
+                        gi = oi;
+                        gph = oph;
+                    }
                 }
             }
-            __syncthreads(); // red_* reuse
-            if (lane == 0) {
+            __syncthreads(); // red_* of step 3 were consumed by thread 0
+            if (lane == 0 && wave * 64 < G) {
                 red_v[wave] = gv;
                 red_i[wave] = gi;
                 red_ph[wave] = gph;
@@ -215,7 +328,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(
             if (tid == 0) {
                 double bv = red_v[0];
                 int bi = red_i[0], bph = red_ph[0];
-                for (int q = 1; q < kPanelThreads / 64; ++q) {
+                for (int q = 1; q * 64 < G; ++q) {
                     if (beats(red_v[q], red_i[q], bv, bi)) {
                         bv = red_v[q];
                         bi = red_i[q];
@@ -225,153 +338,200 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(
                 bc_tau = bv;
                 bc_p = bi;
                 bc_physp = bph;
-                const Slot *srr = &slots[par * kMaxPanelGroups + wr];
-                bc_xr = srr->xr;
-                bc_physr = srr->phys_r;
             }
-            __syncthreads();
         }
+        __syncthreads();
+        if (tid == 0) {
+            const int bi = bc_p, bph = bc_physp;
+            if (bi < r || bi >= n || bph < 0 || bph >= G * R) { // only after a failed wait
+                bc_p = r;
+                bc_physp = 0;
+                bc_fail = 1;
+            }
+        }
+        __syncthreads();
         const int p = bc_p;
-        const double tau = bc_tau;
-        const int physp = bc_physp, physr = bc_physr;
-        const int wp = (p - base) / R;
+        const double tau = bc_fail ? __longlong_as_double(0x7ff8000000000000ll) : bc_tau;
+        const int physp = bc_physp;
 
-        // 5a. pivot row content (L[p][panel] before the exchange), and the old
-        //     row r for the owner of p.
-        if (tid <= j)
-            hrow[tid] = mirror[(size_t)physp * ldm + tid];
-        if (w == wp && p != r && tid <= j)
-            rrow[tid] = mirror[(size_t)physr * ldm + tid];
+        // 5a. the pivot row of L (row p before the exchange): it is the
+        //     previous row for the next step's h.
+        if (multi) {
+            if (tid <= j)
+                hrow[tid] = ld_dev(&mirror[(size_t)physp * ldm + tid]);
+        } else if (exists && pos == p) {
+#pragma unroll
+            for (int q = 0; q < kNS; ++q)
+                hrow[sub + TPR * q] = Lreg[q];
+        }
 
-        // 5b. symmetric exchange r <-> p of the trailing matrix in lower
-        //     storage, one owned row i > r per thread; ycol becomes Y'[i, r].
-        if (rowvalid && sub == 0 && myrow > r) {
-            const size_t cr = (size_t)r * lda, cpv = (size_t)p * lda;
+        // 5b. relabel: the register row of r now holds p, the one of p holds r.
+        if (exists) {
+            if (pos == r)
+                pos = p;
+            else if (pos == p)
+                pos = r;
+        }
+
+        // 5c. symmetric exchange r <-> p of the trailing matrix in lower
+        //     storage, one row i > r per register row; ycol becomes Y'[i, r].
+        if (exists && sub == 0 && pos > r) {
+            double *colr = A + (size_t)r * lda;
             double ynew;
             if (p == r) {
-                ynew = A[cr + myrow];
-            } else if (myrow > p) {
-                const double av = A[cr + myrow];
-                const double bvv = A[cpv + myrow];
-                A[cpv + myrow] = av;
+                ynew = ld_dev(&colr[pos]);
+            } else if (pos > p) {
+                double *colp = A + (size_t)p * lda;
+                const double av = ld_dev(&colr[pos]);
+                const double bvv = ld_dev(&colp[pos]);
+                st_xcd(&colp[pos], av, local);
                 if (last)
-                    A[cr + myrow] = bvv;
+                    st_xcd(&colr[pos], bvv, local);
                 ynew = bvv;
-            } else if (myrow < p) {
-                const double av = A[cr + myrow];
-                const size_t pi = (size_t)myrow * lda + p;
-                const double bvv = A[pi];
-                A[pi] = -av;
+            } else if (pos < p) {
+                double *pi = A + (size_t)pos * lda + p;
+                const double av = ld_dev(&colr[pos]);
+                const double bvv = ld_dev(pi);
+                st_xcd(pi, -av, local);
                 if (last)
-                    A[cr + myrow] = -bvv;
+                    st_xcd(&colr[pos], -bvv, local);
                 ynew = -bvv;
             } else {
-                const double av = A[cr + p];
+                const double av = ld_dev(&colr[p]);
                 if (last)
-                    A[cr + p] = -av;
+                    st_xcd(&colr[p], -av, local);
                 ynew = -av;
             }
             ycol = ynew;
         }
-        __syncthreads();
+        ycol = __shfl(ycol, lane & ~(TPR - 1), 64);
 
-        // 5c. exchange the LDS rows r and p and their physical indices.
-        if (w == wr) {
-            const int lrr = (r - base) - w * R;
-            if (lr == lrr) {
-                for (int a = sub; a <= j; a += TPR)
-                    Lp[(size_t)lrr * ldl + a] = hrow[a];
-                if (sub == 0) {
-                    Lp[(size_t)lrr * ldl + j + 1] = 1.0;
-                    perm[lrr] = physp;
-                }
+        // 5d. new column of L: l_i = x_i / tau for rows i > r (each register
+        //     row keeps its own x); row r gets its unit diagonal.
+        if (exists && pos >= r) {
+            const int a1 = j + 1;
+            const double l = (pos == r) ? 1.0 : ((tau != 0.0) ? xv / tau : 0.0);
+            if (sub == a1 % TPR) {
+                // select into every slot (keeps Lreg in registers: an indexed
+                // store would move the array to scratch memory)
+                const int slot = a1 / TPR;
+#pragma unroll
+                for (int q = 0; q < kNS; ++q)
+                    Lreg[q] = (q == slot) ? l : Lreg[q];
+                if (multi && pos > r)
+                    st_xcd(&mirror[(size_t)phys * ldm + a1], l, local);
             }
         }
-        if (w == wp && p != r) {
-            const int lrp = (p - base) - w * R;
-            if (lr == lrp) {
-                for (int a = sub; a <= j; a += TPR)
-                    Lp[(size_t)lrp * ldl + a] = rrow[a];
-                if (sub == 0) {
-                    perm[lrp] = physr;
-                    xl[lrp] = bc_xr;
-                }
-            }
-        }
-        if (tid == 0)
+        if (tid == 0) {
             tl[j] = tau;
-        if (w == 0 && tid == 0) {
-            t[c] = tau;
-            ipiv[r] = p;
-        }
-        __syncthreads();
-
-        // 5d. new column of L: l_i = x_i / tau for owned rows i > r.
-        if (rowvalid && sub == 0 && myrow > r) {
-            const double l = (tau != 0.0) ? xl[lr] / tau : 0.0;
-            Lp[(size_t)lr * ldl + j + 1] = l;
-            mirror[(size_t)perm[lr] * ldm + j + 1] = l;
+            pl[j] = p;
         }
         __syncthreads();
     }
 
-    // ---- panel end: L into A (shifted one column left), t onto the
-    //      subdiagonal, the carried column, and the skr2k operands.
-    if (rowvalid) {
-        const double *Lrow = Lp + (size_t)lr * ldl;
-        for (int a = sub; a <= nb; a += TPR) {
-            const int col = k0 + a;
-            if (col >= 1 && myrow >= col + 1)
-                A[(size_t)(col - 1) * lda + myrow] = Lrow[a];
+    // ---- panel end: pivots and t, L into A (shifted one column left), t on
+    //      the subdiagonal, the carried column, and the skr2k operands.
+    if (w == 0) {
+        for (int a = tid; a < nb; a += NT) {
+            t[k0 + a] = tl[a];
+            ipiv[k0 + a + 1] = pl[a];
+            A[(size_t)(k0 + a) * lda + (k0 + a + 1)] = tl[a];
         }
-        const int cp = k0 + nb;
-        if (sub == 0 && myrow >= cp + 1)
-            lcar[myrow] = Lrow[nb];
-        if (myrow >= cp && cp < n - 1) {
-            const int nq = (nb + 1) / 2;
-            for (int q = sub; q < nq; q += TPR) {
-                const double vq = Lrow[2 * q + 1];
-                double uq = -tl[2 * q] * Lrow[2 * q];
-                if (2 * q + 2 <= nb)
-                    uq += tl[2 * q + 1] * Lrow[2 * q + 2];
-                uv[(size_t)q * n + myrow] = uq;
-                uv[(size_t)(nq + q) * n + myrow] = vq;
-                uv[(size_t)(2 * nq + q) * n + myrow] = -vq;
-                uv[(size_t)(3 * nq + q) * n + myrow] = uq;
-                if (want32) {
-                    uv32[(size_t)q * n + myrow] = (float)uq;
-                    uv32[(size_t)(nq + q) * n + myrow] = (float)vq;
-                    uv32[(size_t)(2 * nq + q) * n + myrow] = -(float)vq;
-                    uv32[(size_t)(3 * nq + q) * n + myrow] = (float)uq;
+    }
+    const int cp = k0 + nb;
+    if (exists) {
+#pragma unroll
+        for (int q = 0; q < kNS; ++q) {
+            const int a = sub + TPR * q;
+            const int col = k0 + a;
+            if (a <= nb && col >= 1 && pos >= col + 1)
+                A[(size_t)(col - 1) * lda + pos] = Lreg[q];
+            if (a == nb && pos >= cp + 1)
+                lcar[pos] = Lreg[q];
+        }
+    }
+    if (sub == 0)
+        posl[lr] = exists ? pos : -1;
+    if (cp < n - 1) {
+        // U_q = -t_2q L[:,2q] + t_2q+1 L[:,2q+2], V_q = L[:,2q+1] for the rows
+        // >= cp, staged in LDS 32 columns at a time
+        const int nq = (nb + 1) / 2;
+        for (int c0 = 0; c0 < 2 * nq; c0 += 32) {
+            if (exists) {
+#pragma unroll
+                for (int q = 0; q < kNS; ++q) {
+                    const int a = sub + TPR * q;
+                    if (a >= c0 && a <= c0 + 32)
+                        stage[(size_t)lr * 34 + (a - c0)] = (a <= nb) ? Lreg[q] : 0.0;
                 }
             }
+            __syncthreads();
+            const int qlo = c0 / 2, qhi = min(nq, qlo + 16);
+            for (int e = tid; e < R * (qhi - qlo); e += NT) {
+                const int rr = e % R;
+                const int qq = qlo + e / R;
+                const int row = posl[rr];
+                if (row >= cp && row < n) {
+                    const double *srow = stage + (size_t)rr * 34;
+                    const double vq = srow[2 * qq + 1 - c0];
+                    double uq = -tl[2 * qq] * srow[2 * qq - c0];
+                    if (2 * qq + 2 <= nb)
+                        uq += tl[2 * qq + 1] * srow[2 * qq + 2 - c0];
+                    uv[(size_t)qq * n + row] = uq;
+                    uv[(size_t)(nq + qq) * n + row] = vq;
+                    uv[(size_t)(2 * nq + qq) * n + row] = -vq;
+                    uv[(size_t)(3 * nq + qq) * n + row] = uq;
+                    if (want32) {
+                        uv32[(size_t)qq * n + row] = (float)uq;
+                        uv32[(size_t)(nq + qq) * n + row] = (float)vq;
+                        uv32[(size_t)(2 * nq + qq) * n + row] = -(float)vq;
+                        uv32[(size_t)(3 * nq + qq) * n + row] = (float)uq;
+                    }
+                }
+            }
+            __syncthreads();
         }
     }
-    if (w == 0) {
-        for (int a = tid; a < nb; a += kPanelThreads)
-            A[(size_t)(k0 + a) * lda + (k0 + a + 1)] = tl[a];
-    }
+}
+
+// Panel shapes: 512 threads per group, TPR threads per row, kNS register
+// slots per thread holding b + 1 columns; R = 512 / TPR rows per group.
+//   b <= 64:  TPR 1, 65 slots, 512 rows (n = 16384 needs 32 groups: one XCD)
+//   b <= 128: TPR 2, 65 slots, 256 rows
+//   b <= 256: TPR 4, 65 slots, 128 rows
+constexpr int kNT = 512;
+constexpr int kXcdCUs = 32; // CUs per XCD on MI355X
+static int shape_id(int b)
+{
+    if (b + 1 <= 65)
+        return 0;
+    if (b + 1 <= 130)
+        return 1;
+    return 2;
+}
+static int rows_per_group(int b)
+{
+    const int id = shape_id(b);
+    return id == 0 ? 512 : (id == 1 ? 256 : 128);
 }
 
 PanelShape panel_shape(int n, int k0, int b, int max_groups)
 {
     PanelShape sh;
     const int m = n - k0 - 1;
-    int R = 64;
-    while ((m + R - 1) / R > max_groups && R < kPanelThreads)
-        R *= 2;
-    sh.R = R;
-    sh.G = (m + R - 1) / R;
+    sh.R = rows_per_group(b);
+    sh.G = (m + sh.R - 1) / sh.R;
     if (sh.G < 1)
         sh.G = 1;
-    sh.lds = sizeof(double) * ((size_t)R * (b + 2) + 3 * (size_t)(b + 2) + R + b) +
-             sizeof(int) * (size_t)R;
+    (void)max_groups;
+    sh.lds = sizeof(double) * (size_t)sh.R * 34;
     return sh;
 }
 
-hipError_t launch_panel(double *A, int lda, int n, int k0, int nb, int b, double *t,
-                        int *ipiv, const FactorWs &ws, int want32, const PanelShape &sh,
-                        hipStream_t s)
+template <int TPR, int NS>
+static hipError_t launch_t(double *A, int lda, int n, int k0, int nb, int b, double *t,
+                           int *ipiv, const FactorWs &ws, int want32, const PanelShape &sh,
+                           hipStream_t s)
 {
     double *mirror = ws.mirror;
     int ldm = ws.ldm;
@@ -379,17 +539,35 @@ hipError_t launch_panel(double *A, int lda, int n, int k0, int nb, int b, double
     double *uv = ws.uv;
     float *uv32 = ws.uv32;
     Slot *slots = ws.slots;
-    int G = sh.G, R = sh.R;
+    int G = sh.G;
+    int one_xcd = (G > 1 && G <= kXcdCUs) ? 1 : 0;
     void *args[] = {&A, &lda, &n, &k0, &nb, &b, &t, &ipiv, &mirror, &ldm, &lcar,
-                    &uv, &uv32, &want32, &slots, &G, &R};
-    return hipLaunchCooperativeKernel((const void *)panel_kernel, dim3(sh.G),
-                                      dim3(kPanelThreads), args, (unsigned)sh.lds, s);
+                    &uv, &uv32, &want32, &slots, &G, &one_xcd};
+    const void *fn = (const void *)panel_kernel<kNT, TPR, NS>;
+    if (G == 1) // no cross-group exchange: an ordinary launch
+        return hipLaunchKernel(fn, dim3(1), dim3(kNT), args, (unsigned)sh.lds, s);
+    const int grid = one_xcd ? 8 * G : G;
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kNT), args, (unsigned)sh.lds, s);
+}
+
+hipError_t launch_panel(double *A, int lda, int n, int k0, int nb, int b, double *t, int *ipiv,
+                        const FactorWs &ws, int want32, const PanelShape &sh, hipStream_t s)
+{
+    switch (shape_id(b)) {
+    case 0: return launch_t<1, 65>(A, lda, n, k0, nb, b, t, ipiv, ws, want32, sh, s);
+    case 1: return launch_t<2, 65>(A, lda, n, k0, nb, b, t, ipiv, ws, want32, sh, s);
+    default: return launch_t<4, 65>(A, lda, n, k0, nb, b, t, ipiv, ws, want32, sh, s);
+    }
 }
 
 void panel_init_attrs()
 {
-    (void)hipFuncSetAttribute((const void *)panel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        160 * 1024);
+    (void)hipFuncSetAttribute((const void *)panel_kernel<kNT, 1, 65>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)panel_kernel<kNT, 2, 65>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)panel_kernel<kNT, 4, 65>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
 int panel_max_groups(size_t lds_bytes)
@@ -398,9 +576,12 @@ int panel_max_groups(size_t lds_bytes)
     if (!cached_cus)
         cached_cus = device_cu_count();
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)panel_kernel,
-                                                     kPanelThreads, lds_bytes) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                     (const void *)panel_kernel<kNT, 2, 65>, kNT,
+                                                     lds_bytes) != hipSuccess)
         return 0;
+    if (per_cu < 1)
+        per_cu = 1;
     long g = (long)per_cu * cached_cus;
     if (g > kMaxPanelGroups)
         g = kMaxPanelGroups;

@@ -42,7 +42,7 @@ size_t factor_ws_layout(int n, int b, FactorWs *ws, char *base)
     };
     FactorWs w{};
     w.ldm = b + 2;
-    w.mirror = (double *)take(sizeof(double) * nn * (size_t)(b + 2));
+    w.mirror = (double *)take(sizeof(double) * (nn + 512) * (size_t)(b + 2));
     w.lcar = (double *)take(sizeof(double) * nn);
     w.uv = (double *)take(sizeof(double) * nn * (size_t)(4 * nq));
     w.uv32 = (float *)take(sizeof(float) * nn * (size_t)(4 * nq));
@@ -170,7 +170,7 @@ static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int bloc
     for (int k0 = 0; k0 < n - 1; k0 += b) {
         const int nb = (b < n - 1 - k0) ? b : (n - 1 - k0);
         PanelShape sh = panel_shape(n, k0, b, maxg);
-        if (sh.lds > kLdsCap || sh.G > maxg)
+        if (sh.lds > kLdsCap || sh.G > maxg || 8L * sh.G > 8L * maxg)
             return SKLTLT_ENOTSUP;
         int ti = tm_begin(SKLTLT_K_PANEL, s);
         if (launch_panel(A, lda, n, k0, nb, b, t, ipiv, ws, want32, sh, s) != hipSuccess)

@@ -28,6 +28,7 @@
 namespace skl {
 
 constexpr int TM = 128;    // tile rows (i) and columns (j)
+constexpr int TMP = 144;   // padded LDS row (k-rows 1152 B apart: banks shift by 128 B)
 constexpr int KC = 16;     // K chunk staged in LDS
 
 template <typename T> struct MfmaT;
@@ -64,13 +65,15 @@ __device__ __forceinline__ void tile_of(int tau, int *ti, int *tj)
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void skr2k_kernel(double *__restrict__ A, int lda, int n,
-                                                    int cp, int K, const T *__restrict__ uv,
-                                                    int ntiles)
+__global__ __launch_bounds__(256, 2) void skr2k_kernel(double *__restrict__ A, int lda, int n,
+                                                       int cp, int K, const T *__restrict__ uv,
+                                                       int ntiles)
 {
     typedef typename MfmaT<T>::acc4 acc4;
-    __shared__ T sI[KC][TM]; // [U|V] rows i, k-major
-    __shared__ T sJ[KC][TM]; // [-V|U] rows j, k-major
+    // double-buffered operand chunks, k-major, rows padded so that the four
+    // k-rows read by one fragment load fall in different LDS banks
+    __shared__ T sI[2][KC][TMP]; // [U|V] rows i
+    __shared__ T sJ[2][KC][TMP]; // [-V|U] rows j
 
     // XCD-grouped tile order
     const int nwg = gridDim.x;
@@ -92,29 +95,42 @@ __global__ __launch_bounds__(256) void skr2k_kernel(double *__restrict__ A, int 
     const int jb = j0 + wj * 64; // this wave's 64 columns
     const bool active = !(ti == tj && wi == 0 && wj == 1);
 
-    const int lrow = lane & 15; // i offset inside a 16-block / MFMA b-row
-    const int lk = lane >> 4;   // k inside a 4-step, or 4-row group of D
+    const int lrow = lane & 15; // row inside a 16-block
+    const int lk = lane >> 4;   // k inside a 4-step, or row group of D
 
+    // Accumulators.  FP64: start from the C tile itself (loads issued first so
+    // their latency overlaps the operand staging); FP32: start from zero and
+    // add the fp32 product to C in fp64 at the end.
     acc4 acc[4][4];
+    constexpr bool kF64 = sizeof(T) == 8;
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+    for (int bi = 0; bi < 4; ++bi) {
+        const int gi = ib + bi * 16 + lrow;
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj)
-            acc[bi][bj] = acc4{0, 0, 0, 0};
+        for (int bj = 0; bj < 4; ++bj) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gj = jb + bj * 16 + MfmaT<T>::drow(lk, q);
+                T v = 0;
+                if (kF64 && active && gi < n && gj < gi)
+                    v = (T)A[(size_t)gj * lda + gi];
+                acc[bi][bj][q] = v;
+            }
+        }
+    }
 
-    const int nK = 2 * K; // column count of [U|V|-V|U] is 2K, K = 2k
-    (void)nK;
-    const T *opI = uv;                  // columns [0, K)
-    const T *opJ = uv + (size_t)K * n;  // columns [K, 2K)
+    const T *opI = uv;                 // columns [0, K)
+    const T *opJ = uv + (size_t)K * n; // columns [K, 2K)
+    const int nk = (K + KC - 1) / KC;
+    constexpr int PER = (KC * TM) / 256; // elements per thread per operand and chunk
+    T ri[PER], rj[PER];
 
-    for (int k0 = 0; k0 < K; k0 += KC) {
-        // stage KC x 128 of each operand (column-major, ld = n)
+    auto load_chunk = [&](int kc) {
 #pragma unroll
-        for (int q = 0; q < (KC * TM) / 256; ++q) {
+        for (int q = 0; q < PER; ++q) {
             const int e = tid + q * 256;
             const int rr = e % TM;
-            const int kk = e / TM;
-            const int k = k0 + kk;
+            const int k = kc * KC + e / TM;
             const int gi = i0 + rr, gj = j0 + rr;
             T vi = 0, vj = 0;
             if (k < K) {
@@ -123,20 +139,41 @@ __global__ __launch_bounds__(256) void skr2k_kernel(double *__restrict__ A, int 
                 if (gj < n)
                     vj = opJ[(size_t)k * n + gj];
             }
-            sI[kk][rr] = vi;
-            sJ[kk][rr] = vj;
+            ri[q] = vi;
+            rj[q] = vj;
         }
-        __syncthreads();
+    };
+    auto store_chunk = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * 256;
+            sI[buf][e / TM][e % TM] = ri[q];
+            sJ[buf][e / TM][e % TM] = rj[q];
+        }
+    };
+
+    load_chunk(0);
+    store_chunk(0);
+    if (nk > 1)
+        load_chunk(1);
+    __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+        const int cur = kc & 1;
+        if (kc + 1 < nk) {
+            store_chunk(cur ^ 1); // buffer freed by the barrier ending step kc-1
+            if (kc + 2 < nk)
+                load_chunk(kc + 2); // in flight during this chunk's MFMAs
+        }
         if (active) {
 #pragma unroll
             for (int ks = 0; ks < KC; ks += 4) {
                 T fa[4], fb[4];
 #pragma unroll
                 for (int bj = 0; bj < 4; ++bj)
-                    fa[bj] = sJ[ks + lk][wj * 64 + bj * 16 + lrow];
+                    fa[bj] = sJ[cur][ks + lk][wj * 64 + bj * 16 + lrow];
 #pragma unroll
                 for (int bi = 0; bi < 4; ++bi)
-                    fb[bi] = sI[ks + lk][wi * 64 + bi * 16 + lrow];
+                    fb[bi] = sI[cur][ks + lk][wi * 64 + bi * 16 + lrow];
 #pragma unroll
                 for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
@@ -149,7 +186,7 @@ __global__ __launch_bounds__(256) void skr2k_kernel(double *__restrict__ A, int 
     if (!active)
         return;
 
-    // D[m][nn] (m = MfmaT::drow(lane/16, q) : column j, nn = lane%16 : row i) += C
+    // D[m][nn] (m = MfmaT::drow(lane/16, q) : column j, nn = lane%16 : row i)
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi) {
         const int gi = ib + bi * 16 + lrow;
@@ -162,7 +199,10 @@ __global__ __launch_bounds__(256) void skr2k_kernel(double *__restrict__ A, int 
                 const int gj = jb + bj * 16 + MfmaT<T>::drow(lk, q);
                 if (gj < gi) {
                     double *cptr = A + (size_t)gj * lda + gi;
-                    *cptr = *cptr + (double)acc[bi][bj][q];
+                    if (kF64)
+                        *cptr = (double)acc[bi][bj][q];
+                    else
+                        *cptr = *cptr + (double)acc[bi][bj][q];
                 }
             }
         }
