@@ -18,6 +18,7 @@
 // arithmetic of a matrix depends only on that matrix and on bs, never on
 // which workgroup runs it or on the other matrices.
 #include "../../include/skltlt.h"
+#include "batched_table.h"
 #include "common.h"
 
 #include <climits>
@@ -38,10 +39,10 @@ __device__ __forceinline__ bool beats_b(double av, int ai, double bv, int bi)
 // Panel width for order n (block_size = 0): from the tuning table.
 __device__ __host__ inline int batched_bs_for(int n)
 {
-    // measured on MI355X by the batched tuner (tune_batched.py)
-    if (n <= 64)
-        return 8;
-    return 16;
+    for (const BatchedTune &e : kBatchedTune)
+        if (n <= e.n_max)
+            return e.bs;
+    return kBMaxBs;
 }
 
 struct BatchShared {

@@ -1,0 +1,348 @@
+"""Continuous-batching server for Pfaffian / factorization requests.
+
+Requests of uneven order arrive over time.  The scheduler admits them in
+arrival order while the device-memory budget allows (back-pressure when it is
+full), keeps every admitted request's matrix and factors on the device, and
+overlaps their work on the GPU:
+
+* small FP64 requests (n <= ``small_n``) are collected and factored together
+  by one ``skltlt_batched`` launch; requests admitted while a batch runs join
+  the next batch, which starts as soon as the batch stream is free;
+* the others run ``skltlt_pfaffian`` each, spread over a pool of streams.
+
+Completion is detected by polling HIP events, never by blocking the device.
+Latency is measured from a request's arrival to the host observing its
+completion.  The executor is pluggable: ``GpuExecutor`` drives the library,
+``FakeExecutor`` runs the same scheduling logic on the CPU (tests of
+admission, back-pressure, failure handling and latency accounting).
+
+A request's result does not depend on which other requests share the GPU or
+its batch: the batched kernel and the blocked factorization compute each
+matrix independently and deterministically.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+from typing import Callable, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    n: int
+    precision: int = 0            # 0 FP64, 1 FP32 update
+    arrival: float = 0.0          # seconds on the server clock
+    seed: int = 0                 # for device-side generation of the input
+    matrix: Optional[np.ndarray] = None  # host input (strict lower used), optional
+    want_factors: bool = False    # keep A/t/ipiv on the device for the caller
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    n: int
+    log_abs_pf: float
+    sign: int
+    arrival: float
+    admitted: float
+    done: float
+    path: str
+    error: Optional[str] = None
+    factors: object = None
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+def request_bytes(n: int, precision: int = 0) -> int:
+    """Device bytes a request holds while admitted (matrix, t, ipiv, work)."""
+    from . import binding
+    b = binding.default_block_size(max(n, 1))
+    ws = binding.workspace_size(max(n, 1), b, precision) if n > 256 else 0
+    return 8 * n * n + 16 * n + ws + 4096
+
+
+class FakeExecutor:
+    """CPU stand-in: a request 'runs' for a modelled time and its Pfaffian is
+    computed by a supplied function (e.g. the oracle).  Same interface as the
+    GPU executor."""
+
+    def __init__(self, clock: Callable[[], float], duration: Callable[[Request], float],
+                 pf: Optional[Callable[[Request], tuple]] = None,
+                 fail: Optional[Callable[[Request], bool]] = None, bytes_of=None):
+        self.clock = clock
+        self.duration = duration
+        self.pf = pf
+        self.fail = fail
+        self.inflight = []
+        self.bytes_of = bytes_of or (lambda r: 8 * r.n * r.n + 4096)
+
+    def nbytes(self, req):
+        return self.bytes_of(req)
+
+    def launch_batch(self, reqs):
+        t = self.clock()
+        end = t + sum(self.duration(r) for r in reqs) / max(len(reqs), 1)
+        self.inflight.append((end, reqs, "batched"))
+
+    def launch_single(self, req):
+        self.inflight.append((self.clock() + self.duration(req), [req], "single"))
+
+    def batch_busy(self):
+        return any(p == "batched" for _, _, p in self.inflight)
+
+    def poll(self):
+        now = self.clock()
+        done, keep = [], []
+        for item in self.inflight:
+            (done if item[0] <= now else keep).append(item)
+        self.inflight = keep
+        out = []
+        for _, reqs, path in done:
+            for r in reqs:
+                if self.fail and self.fail(r):
+                    out.append((r, float("nan"), 0, path, "device error"))
+                    continue
+                la, sg = self.pf(r) if self.pf else (0.0, 1)
+                out.append((r, la, sg, path, None))
+        return out
+
+    def idle(self):
+        return not self.inflight
+
+
+class GpuExecutor:
+    """Drives libskltlt on cuda:0: one batch stream, a pool of streams."""
+
+    def __init__(self, n_streams: int = 4, small_n: int = 256, device="cuda"):
+        import torch
+        from . import binding
+        self.torch = torch
+        self.binding = binding
+        self.device = device
+        self.small_n = small_n
+        self.batch_stream = torch.cuda.Stream(device=device)
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        self.next_stream = 0
+        self.inflight = []  # (event, payload)
+
+    def nbytes(self, req):
+        return request_bytes(req.n, req.precision)
+
+    def _materialize(self, req, stream):
+        """Device input for a request: the host matrix if given, else seeded
+        N(0,1) entries drawn on the device (only the strict lower triangle is
+        read by the library)."""
+        torch = self.torch
+        n = req.n
+        with torch.cuda.stream(stream):
+            if req.matrix is not None:
+                host = torch.from_numpy(np.asfortranarray(req.matrix, dtype=np.float64))
+                dev = torch.empty_strided((n, n), (1, max(n, 1)), dtype=torch.float64,
+                                          device=self.device)
+                dev.copy_(host, non_blocking=False)
+            else:
+                g = torch.Generator(device=self.device)
+                g.manual_seed(int(req.seed))
+                dev = torch.randn((n, n), generator=g, dtype=torch.float64,
+                                  device=self.device).t()  # column-major view
+        return dev
+
+    def launch_batch(self, reqs):
+        torch, binding = self.torch, self.binding
+        s = self.batch_stream
+        with torch.cuda.stream(s):
+            mats = [self._materialize(r, s) for r in reqs]
+            ns = [r.n for r in reqs]
+            ts = [torch.empty(max(n - 1, 1), dtype=torch.float64, device=self.device) for n in ns]
+            ps = [torch.empty(max(n, 1), dtype=torch.int32, device=self.device) for n in ns]
+            n_dev = torch.tensor(ns, dtype=torch.int32, device=self.device)
+            lda = torch.tensor([max(n, 1) for n in ns], dtype=torch.int32, device=self.device)
+            A_ptr = torch.tensor([m.data_ptr() for m in mats], dtype=torch.int64, device=self.device)
+            t_ptr = torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64, device=self.device)
+            p_ptr = torch.tensor([p.data_ptr() for p in ps], dtype=torch.int64, device=self.device)
+            la = torch.empty(len(reqs), dtype=torch.float64, device=self.device)
+            sg = torch.empty(len(reqs), dtype=torch.int32, device=self.device)
+            info = torch.empty(len(reqs), dtype=torch.int32, device=self.device)
+            work = binding.alloc_workspace(binding.batched_workspace_size(len(reqs)), self.device)
+            binding.batched(n_dev, A_ptr, lda, t_ptr, p_ptr, la, sg, info, max(ns), 0,
+                            binding.FP64, work, s)
+            la_h = torch.empty(len(reqs), dtype=torch.float64, pin_memory=True)
+            sg_h = torch.empty(len(reqs), dtype=torch.int32, pin_memory=True)
+            la_h.copy_(la, non_blocking=True)
+            sg_h.copy_(sg, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        keep = (mats, ts, ps, n_dev, lda, A_ptr, t_ptr, p_ptr, la, sg, info, work)
+        self.inflight.append((ev, ("batched", reqs, la_h, sg_h, keep)))
+
+    def launch_single(self, req):
+        torch, binding = self.torch, self.binding
+        s = self.streams[self.next_stream]
+        self.next_stream = (self.next_stream + 1) % len(self.streams)
+        with torch.cuda.stream(s):
+            A = self._materialize(req, s)
+            n = req.n
+            t = torch.empty(max(n - 1, 1), dtype=torch.float64, device=self.device)
+            ip = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+            la = torch.empty(1, dtype=torch.float64, device=self.device)
+            sg = torch.empty(1, dtype=torch.int32, device=self.device)
+            work = binding.alloc_workspace(
+                binding.workspace_size(max(n, 1), 0, req.precision), self.device)
+            binding.pfaffian(A, t, ip, la, sg, 0, req.precision, work, s)
+            la_h = torch.empty(1, dtype=torch.float64, pin_memory=True)
+            sg_h = torch.empty(1, dtype=torch.int32, pin_memory=True)
+            la_h.copy_(la, non_blocking=True)
+            sg_h.copy_(sg, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        self.inflight.append((ev, ("single", [req], la_h, sg_h, (A, t, ip, la, sg, work))))
+
+    def batch_busy(self):
+        return any(p[0] == "batched" for _, p in self.inflight)
+
+    def poll(self):
+        out, keep = [], []
+        for ev, payload in self.inflight:
+            if ev.query():
+                path, reqs, la_h, sg_h, bufs = payload
+                for k, r in enumerate(reqs):
+                    out.append((r, float(la_h[k]), int(sg_h[k]), path, None))
+            else:
+                keep.append((ev, payload))
+        self.inflight = keep
+        return out
+
+    def idle(self):
+        return not self.inflight
+
+
+class Server:
+    """Admission by memory budget, continuous batching, latency accounting."""
+
+    def __init__(self, executor, budget_bytes: int = 64 << 30, small_n: int = 256,
+                 max_batch: int = 4096, max_inflight_single: int = 64,
+                 clock: Callable[[], float] = time.perf_counter):
+        self.ex = executor
+        self.budget = budget_bytes
+        self.small_n = small_n
+        self.max_batch = max_batch
+        self.max_inflight_single = max_inflight_single
+        self.clock = clock
+        self.used = 0
+        self.peak_used = 0
+        self.waiting = collections.deque()   # arrived, not admitted (FIFO)
+        self.pending_small = []              # admitted, waiting for the next batch
+        self.inflight_single = 0
+        self.held = {}                       # rid -> bytes held
+        self.admit_time = {}
+        self.results = []
+        self.rejected = []
+
+    def submit(self, req: Request):
+        if req.n < 0 or req.n > 1 << 16:
+            self.rejected.append((req, "invalid order"))
+            return
+        if req.matrix is not None and not np.all(np.isfinite(np.tril(req.matrix, -1))):
+            self.rejected.append((req, "non-finite input"))
+            return
+        if self.ex.nbytes(req) > self.budget:
+            self.rejected.append((req, "larger than the memory budget"))
+            return
+        self.waiting.append(req)
+
+    def _admit(self):
+        now = self.clock()
+        while self.waiting:
+            r = self.waiting[0]
+            need = self.ex.nbytes(r)
+            small = r.n <= self.small_n
+            if self.used + need > self.budget:
+                break  # back-pressure: FIFO, no overtaking
+            if not small and self.inflight_single >= self.max_inflight_single:
+                break
+            self.waiting.popleft()
+            self.used += need
+            self.peak_used = max(self.peak_used, self.used)
+            self.held[r.rid] = need
+            self.admit_time[r.rid] = now
+            if small:
+                self.pending_small.append(r)
+            else:
+                self.inflight_single += 1
+                self.ex.launch_single(r)
+
+    def _launch_batch(self):
+        if self.pending_small and not self.ex.batch_busy():
+            reqs = self.pending_small[: self.max_batch]
+            self.pending_small = self.pending_small[self.max_batch:]
+            self.ex.launch_batch(reqs)
+
+    def _collect(self):
+        now = self.clock()
+        for r, la, sg, path, err in self.ex.poll():
+            self.used -= self.held.pop(r.rid)
+            if path == "single":
+                self.inflight_single -= 1
+            self.results.append(Result(r.rid, r.n, la, sg, r.arrival,
+                                       self.admit_time.pop(r.rid), now, path, err))
+
+    def tick(self):
+        self._collect()
+        self._admit()
+        self._launch_batch()
+
+    def busy(self):
+        return bool(self.waiting or self.pending_small or not self.ex.idle())
+
+    def run(self, requests, sleep_s: float = 20e-6, time_limit_s: float = 3600.0):
+        """Replay ``requests`` (sorted by arrival, seconds from start) in real
+        time and return the results."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        t0 = self.clock()
+        i = 0
+        while i < len(reqs) or self.busy():
+            now = self.clock() - t0
+            while i < len(reqs) and reqs[i].arrival <= now:
+                r = reqs[i]
+                r.arrival = t0 + r.arrival
+                self.submit(r)
+                i += 1
+            self.tick()
+            if now > time_limit_s:
+                raise TimeoutError("serving run exceeded its time limit")
+            if i < len(reqs) and not self.busy():
+                wait = reqs[i].arrival - (self.clock() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 1e-3))
+            elif sleep_s:
+                time.sleep(sleep_s)
+        return self.results
+
+
+def summarize(results, wall_s: float):
+    ok = [r for r in results if r.error is None]
+    lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    return {
+        "requests": len(results),
+        "errors": len(results) - len(ok),
+        "solves_per_s": len(ok) / wall_s if wall_s > 0 else 0.0,
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "mean_ms": float(lat.mean() * 1e3),
+        "batched_fraction": float(np.mean([r.path == "batched" for r in ok])) if ok else 0.0,
+    }
+
+
+def make_requests(count: int, seed: int, rate_per_s: float, lo=32, hi=2048, p_fp32=0.5):
+    sizes, prec, arrivals, seeds = __import__(
+        "paper_2411_09859_amd.inputs", fromlist=["serving_requests"]).serving_requests(
+        count, seed, rate_per_s, lo, hi, p_fp32)
+    return [Request(rid=k, n=int(sizes[k]), precision=int(prec[k]), arrival=float(arrivals[k]),
+                    seed=int(seeds[k])) for k in range(count)]

@@ -1,0 +1,90 @@
+"""Autotuner for the batched kernel's panel width per matrix order.
+
+For each size class it times skltlt_batched on a seeded batch of that class
+for every candidate panel width (HIP events, median of a few repetitions) and
+keeps the fastest.  The result is written twice: ``tune_batched.json`` (the
+measurements) and ``csrc/batched_table.h`` (the compiled-in lookup used when
+block_size = 0).  Rebuild the library after tuning.
+
+    python -m paper_2411_09859_amd.tune_batched [--count 512]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+
+import numpy as np
+
+from . import binding, inputs
+from .batch import Arena
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CLASSES = [(16, 32), (34, 64), (66, 96), (98, 128), (130, 160), (162, 192), (194, 224), (226, 256)]
+CANDIDATES = [2, 4, 6, 8, 12, 16]
+
+
+def time_arena(torch, arena, bs, reps=3):
+    ts = []
+    for _ in range(reps + 1):
+        arena.restore()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        arena.run(block_size=bs)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts[1:]))
+
+
+def tune(count=512, seed=7, verbose=True):
+    import torch
+    table = []
+    meas = {}
+    for lo, hi in CLASSES:
+        sizes, sing = inputs.batch_sizes(count, seed + lo, lo=lo, hi=hi, singular_fraction=0.0)
+        mats = inputs.batch_matrices(sizes, sing, seed + lo)
+        arena = Arena(mats)
+        res = {}
+        for bs in CANDIDATES:
+            res[bs] = time_arena(torch, arena, bs)
+        best = min(res, key=res.get)
+        meas[f"{lo}-{hi}"] = {"ms": res, "best": best, "count": count}
+        table.append((hi, best))
+        if verbose:
+            print(f"[tune] n in [{lo},{hi}]: " + " ".join(f"bs{b}={t:.2f}ms" for b, t in res.items())
+                  + f" -> {best}", flush=True)
+    return table, meas
+
+
+def write_outputs(table, meas):
+    with open(os.path.join(PKG, "tune_batched.json"), "w") as f:
+        json.dump({"device": "MI355X (gfx950)", "classes": meas}, f, indent=1)
+    lines = ["// Panel width of the batched kernel per matrix order, measured on MI355X",
+             "// by paper_2411_09859_amd/tune_batched.py (written by the tuner).",
+             "#pragma once",
+             "namespace skl {",
+             "struct BatchedTune { int n_max; int bs; };",
+             "constexpr BatchedTune kBatchedTune[] = {"]
+    lines += [f"    {{{hi}, {bs}}}," for hi, bs in table]
+    lines += ["};", "}  // namespace skl", ""]
+    with open(os.path.join(PKG, "csrc", "batched_table.h"), "w") as f:
+        f.write("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--count", type=int, default=512)
+    ap.add_argument("--no-write", action="store_true")
+    args = ap.parse_args()
+    binding.lib()
+    table, meas = tune(args.count)
+    if not args.no_write:
+        write_outputs(table, meas)
+    print(json.dumps({"table": table}))
+
+
+if __name__ == "__main__":
+    main()
