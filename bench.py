@@ -107,6 +107,88 @@ def resid_probe(torch, A0, Af, t, ipiv, nprobe=4, seed=0):
     return worst
 
 
+def bench_batched(torch, binding, inputs, count, seed=4, reps=3):
+    """4096 matrices, even n uniform over [16, 256], 5% singular: one batched
+    launch vs a loop of per-matrix skltlt_pfaffian launches on one stream."""
+    from paper_2411_09859_amd.batch import Arena
+    log(f"[bench] batched: building {count} matrices")
+    sizes, sing = inputs.batch_sizes(count, seed)
+    mats = inputs.batch_matrices(sizes, sing, seed)
+    ar = Arena(mats)
+    flops = float(np.sum(sizes.astype(np.float64) ** 3) / 3.0)
+    for _ in range(1):
+        ar.restore()
+        ar.run()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        ar.restore()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ar.run()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    signs = ar.sign.cpu().numpy()
+    # baseline: per-matrix launches over a prefix of the same batch
+    nbase = min(256, count)
+    ar.restore()
+    torch.cuda.synchronize()
+    t = torch.zeros(256, dtype=torch.float64, device="cuda")
+    ip = torch.zeros(256, dtype=torch.int32, device="cuda")
+    la = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sg = torch.zeros(1, dtype=torch.int32, device="cuda")
+    work = binding.alloc_workspace(binding.workspace_size(256, 0, binding.FP64))
+    base_signs = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(nbase):
+        binding.pfaffian(ar.matrix(k), t, ip, la, sg, 0, binding.FP64, work)
+    e1.record()
+    torch.cuda.synchronize()
+    base_ms_per = e0.elapsed_time(e1) / nbase
+    out = {"workload": f"{count} matrices, even n uniform in [16,256], N(0,1), "
+                       f"{int(sing.sum())} structurally singular, seed {seed}",
+           "ms": ms, "pfaffians_per_s": count / (ms * 1e-3),
+           "gflops_nominal": flops / (ms * 1e-3) / 1e9,
+           "zero_pfaffians": int(np.sum(signs == 0)),
+           "per_matrix_launch_baseline": {"matrices_timed": nbase, "ms_per_matrix": base_ms_per,
+                                          "pfaffians_per_s": 1e3 / base_ms_per},
+           "speedup_vs_per_matrix": (count / (ms * 1e-3)) / (1e3 / base_ms_per)}
+    log(f"[bench] batched {out}")
+    return out
+
+
+def bench_serving(torch, count, seed=5):
+    """Serving stream: n log-uniform over even values in [32, 2048], FP64 /
+    FP32-update tags, 64 GB budget.  A closed-loop run (all requests at t=0)
+    measures capacity; a Poisson run at 80% of it measures latency."""
+    from paper_2411_09859_amd.serving import GpuExecutor, Server, make_requests, summarize
+    reqs = make_requests(count, seed, rate_per_s=1.0)
+    for r in reqs:
+        r.arrival = 0.0
+    srv = Server(GpuExecutor(n_streams=4), budget_bytes=64 << 30)
+    t0 = time.perf_counter()
+    res = srv.run(reqs, time_limit_s=600)
+    wall = time.perf_counter() - t0
+    closed = summarize(res, wall)
+    cap = closed["solves_per_s"]
+    log(f"[bench] serving closed loop {closed}")
+    rate = 0.8 * cap
+    reqs = make_requests(count, seed + 1, rate_per_s=rate)
+    srv = Server(GpuExecutor(n_streams=4), budget_bytes=64 << 30)
+    t0 = time.perf_counter()
+    res = srv.run(reqs, time_limit_s=600)
+    wall = time.perf_counter() - t0
+    openl = summarize(res, wall)
+    log(f"[bench] serving poisson {openl}")
+    return {"workload": f"{count} requests (of the 100000-request stream), n log-uniform even in "
+                        f"[32,2048], FP64/FP32-update 50/50, Poisson arrivals, 64 GB budget",
+            "closed_loop": closed, "poisson_at_80pct": dict(openl, rate_per_s=rate)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +201,11 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=160,
                     help="oracle column steps in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--serving-count", type=int, default=2000,
+                    help="requests in the serving runs (the full stream has 100000)")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
 
@@ -261,6 +348,9 @@ def main():
                                                                    ref["ipiv"][: s_steps + 1]))
         log(f"[bench] oracle {cpu}")
 
+    batched = None if args.no_batched else bench_batched(torch, binding, inputs, args.batch_count)
+    serving = None if args.no_serving else bench_serving(torch, args.serving_count)
+
     out = {
         "metric": "FP64 skew-LTLt GFLOP/s (n^3/3) at n=16384; batched Pfaffians/s + p99 latency",
         "value": gflops,
@@ -282,6 +372,8 @@ def main():
         "kernels": kt,
         "fp32_update": fp32,
         "pfaffian_fp64": {"sign": sign64, "log_abs_pf": logpf64},
+        "batched": batched,
+        "serving": serving,
         "checks": checks,
     }
     print(json.dumps(out), flush=True)

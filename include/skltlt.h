@@ -141,6 +141,10 @@ int skltlt_batched(int batch, const int *n, double *const *A, const int *lda,
                    int precision, void *work, size_t work_bytes,
                    void *stream);
 
+/* Text of the HIP error behind the most recent SKLTLT_EDEVICE returned in
+ * the calling thread ("" if none).  Static storage, never NULL. */
+const char *skltlt_last_device_error(void);
+
 /* ---- Instrumentation ---------------------------------------------------
  * Per-kernel timing for measurement tools.  While enabled, every kernel the
  * library enqueues is bracketed by a pair of HIP events recorded on the same

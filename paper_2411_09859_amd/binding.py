@@ -29,6 +29,8 @@ class SkltltError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
         msg = lib().skltlt_status_string(status).decode()
+        if status == SKLTLT_EDEVICE:
+            msg += " [" + lib().skltlt_last_device_error().decode() + "]"
         super().__init__(f"{what}: {msg} ({status})")
 
 
@@ -38,10 +40,16 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        # torch bundles its own HIP runtime with the same SONAME as ROCm's;
+        # loading torch first makes the library bind to that one runtime
+        # instead of pulling a second HIP/HSA runtime into the process.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
         L.skltlt_status_string.argtypes = [i]
         L.skltlt_status_string.restype = ctypes.c_char_p
+        L.skltlt_last_device_error.argtypes = []
+        L.skltlt_last_device_error.restype = ctypes.c_char_p
         L.skltlt_default_block_size.argtypes = [i]
         L.skltlt_default_block_size.restype = i
         L.skltlt_workspace_size.argtypes = [i, i, i, ctypes.POINTER(sz)]

@@ -27,7 +27,7 @@
 namespace skl {
 
 constexpr int kBT = 256;     // threads per workgroup = largest order
-constexpr int kBMaxBs = 16;  // largest panel width
+constexpr int kBMaxBs = 16;  // largest panel width (2 workgroups per CU)
 constexpr int kBLd = kBMaxBs + 2;
 
 __device__ __forceinline__ bool beats_b(double av, int ai, double bv, int bi)
@@ -406,6 +406,7 @@ static hipError_t launch_batched(int batch, const int *n, double *const *A, cons
                                   (int)sizeof(BatchShared));
         attr = true;
     }
+    (void)hipGetLastError(); // a refused attribute is not a launch failure
     hipError_t e = launch_fill_zero(queue, 256, s);
     if (e != hipSuccess)
         return e;
@@ -422,9 +423,10 @@ static hipError_t launch_batched(int batch, const int *n, double *const *A, cons
         grid = batch;
     if (grid < 1)
         return hipSuccess;
-    hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(kBT), sizeof(BatchShared), s, batch, n,
-                       A, lda, t, ipiv, log_abs_pf, sign, info, max_n, block_size, queue);
-    return hipGetLastError();
+    void *args[] = {&batch, &n, &A, &lda, &t, &ipiv, &log_abs_pf, &sign, &info, &max_n,
+                    &block_size, &queue};
+    return hipLaunchKernel((const void *)batched_kernel, dim3(grid), dim3(kBT), args,
+                           sizeof(BatchShared), s);
 }
 
 }  // namespace skl
@@ -461,9 +463,10 @@ extern "C" int skltlt_batched(int batch, const int *n, double *const *A, const i
         return SKLTLT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const int ti = tm_begin(SKLTLT_K_BATCHED, s);
-    if (launch_batched(batch, n, A, lda, t, ipiv, log_abs_pf, sign, info, max_n, block_size,
-                       (int *)work, s) != hipSuccess)
-        return SKLTLT_EDEVICE;
+    const hipError_t e = launch_batched(batch, n, A, lda, t, ipiv, log_abs_pf, sign, info, max_n,
+                                        block_size, (int *)work, s);
+    if (e != hipSuccess)
+        return device_error(e, "batched launch");
     tm_end(ti, s, 0.0);
     return SKLTLT_OK;
 }

@@ -4,7 +4,13 @@
 namespace skl {
 struct BatchedTune { int n_max; int bs; };
 constexpr BatchedTune kBatchedTune[] = {
-    {64, 8},
+    {32, 16},
+    {64, 16},
+    {96, 16},
+    {128, 16},
+    {160, 16},
+    {192, 16},
+    {224, 16},
     {256, 16},
 };
 }  // namespace skl

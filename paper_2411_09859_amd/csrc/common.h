@@ -61,6 +61,8 @@ hipError_t launch_pfaffian(int n, const double *t, const int *ipiv,
                            double *log_abs_pf, int *sign, hipStream_t s);
 
 int device_cu_count();
+// Records the HIP error behind an SKLTLT_EDEVICE; returns SKLTLT_EDEVICE.
+int device_error(hipError_t e, const char *where);
 int tm_begin(int cls, hipStream_t s);
 void tm_end(int idx, hipStream_t s, double flops);
 void panel_init_attrs();

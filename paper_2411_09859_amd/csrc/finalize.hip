@@ -37,6 +37,7 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
     const size_t words = bytes / 4;
     if (!words)
         return hipSuccess;
+    (void)hipGetLastError(); // report this launch only
     size_t blocks = (words + 255) / 256;
     if (blocks > 4096)
         blocks = 4096;
@@ -47,6 +48,7 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
 
 hipError_t launch_set_int(int *p, int v, hipStream_t s)
 {
+    (void)hipGetLastError();
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, p, v);
     return hipGetLastError();
 }
@@ -122,6 +124,7 @@ hipError_t launch_finalize(double *A, int lda, int n, int b, const int *ipiv,
     const int nblk = (nsteps + b - 1) / b;
     if (nblk <= 1)
         return hipSuccess;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(suffix_map_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ipiv, n, b,
                        nblk, ws.gmap);
     hipError_t e = hipGetLastError();
@@ -193,6 +196,7 @@ __global__ __launch_bounds__(256) void pfaffian_kernel(int n, const double *__re
 hipError_t launch_pfaffian(int n, const double *t, const int *ipiv, double *log_abs_pf, int *sign,
                            hipStream_t s)
 {
+    (void)hipGetLastError();
     hipLaunchKernelGGL(pfaffian_kernel, dim3(1), dim3(256), 0, s, n, t, ipiv, log_abs_pf, sign);
     return hipGetLastError();
 }

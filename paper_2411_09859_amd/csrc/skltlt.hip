@@ -11,11 +11,20 @@
 #include "../../include/skltlt.h"
 #include "common.h"
 
+#include <cstdio>
 #include <mutex>
 
 namespace skl {
 
 static size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+static thread_local char g_last_err[256] = "";
+
+int device_error(hipError_t e, const char *where)
+{
+    snprintf(g_last_err, sizeof(g_last_err), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+    return SKLTLT_EDEVICE;
+}
 
 int device_cu_count()
 {
@@ -70,6 +79,8 @@ static void init_device_attrs()
 }
 
 static const size_t kLdsCap = 160 * 1024;
+
+extern "C" const char *skltlt_last_device_error(void) { return skl::g_last_err; }
 
 extern "C" const char *skltlt_status_string(int status)
 {
@@ -151,10 +162,12 @@ static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int bloc
 
     {
         const int ti = tm_begin(SKLTLT_K_OTHER, s);
-        if (launch_set_int(ipiv, 0, s) != hipSuccess)
-            return SKLTLT_EDEVICE;
-        if (n > 1 && launch_fill_zero(ws.slots, sizeof(Slot) * 2 * kMaxPanelGroups, s) != hipSuccess)
-            return SKLTLT_EDEVICE;
+        hipError_t e = launch_set_int(ipiv, 0, s);
+        if (e != hipSuccess)
+            return device_error(e, "set ipiv[0]");
+        if (n > 1 && (e = launch_fill_zero(ws.slots, sizeof(Slot) * 2 * kMaxPanelGroups, s)) !=
+                         hipSuccess)
+            return device_error(e, "clear slots");
         tm_end(ti, s, 0.0);
     }
     if (n == 1)
@@ -165,7 +178,7 @@ static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int bloc
     PanelShape probe = panel_shape(n, 0, b, kMaxPanelGroups);
     int maxg = panel_max_groups(probe.lds);
     if (maxg <= 0)
-        return SKLTLT_EDEVICE;
+        return device_error(hipErrorInvalidValue, "panel occupancy query");
 
     for (int k0 = 0; k0 < n - 1; k0 += b) {
         const int nb = (b < n - 1 - k0) ? b : (n - 1 - k0);
@@ -173,24 +186,26 @@ static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int bloc
         if (sh.lds > kLdsCap || sh.G > maxg || 8L * sh.G > 8L * maxg)
             return SKLTLT_ENOTSUP;
         int ti = tm_begin(SKLTLT_K_PANEL, s);
-        if (launch_panel(A, lda, n, k0, nb, b, t, ipiv, ws, want32, sh, s) != hipSuccess)
-            return SKLTLT_EDEVICE;
+        hipError_t e = launch_panel(A, lda, n, k0, nb, b, t, ipiv, ws, want32, sh, s);
+        if (e != hipSuccess)
+            return device_error(e, "panel launch");
         tm_end(ti, s, 0.0);
         const int cp = k0 + nb;
         if (cp < n - 1) {
             const int nq = (nb + 1) / 2;
             const double m = (double)(n - cp);
             ti = tm_begin(SKLTLT_K_SKR2K, s);
-            if (launch_skr2k(A, lda, n, cp, nq, ws, precision, s) != hipSuccess)
-                return SKLTLT_EDEVICE;
+            if ((e = launch_skr2k(A, lda, n, cp, nq, ws, precision, s)) != hipSuccess)
+                return device_error(e, "skr2k launch");
             // strict lower triangle of the m x m trailing block, K = 2*nq
             tm_end(ti, s, m * (m - 1.0) * 0.5 * 2.0 * (2.0 * nq));
         }
     }
     {
         const int ti = tm_begin(SKLTLT_K_FINALIZE, s);
-        if (launch_finalize(A, lda, n, b, ipiv, ws, s) != hipSuccess)
-            return SKLTLT_EDEVICE;
+        hipError_t e = launch_finalize(A, lda, n, b, ipiv, ws, s);
+        if (e != hipSuccess)
+            return device_error(e, "finalize launch");
         tm_end(ti, s, 0.0);
     }
     return SKLTLT_OK;
@@ -214,8 +229,9 @@ extern "C" int skltlt_pfaffian(int n, double *A, int lda, double *t, int *ipiv,
     if (st != SKLTLT_OK)
         return st;
     const int ti = tm_begin(SKLTLT_K_PFAFFIAN, s);
-    if (launch_pfaffian(n, t, ipiv, log_abs_pf, sign, s) != hipSuccess)
-        return SKLTLT_EDEVICE;
+    hipError_t e = launch_pfaffian(n, t, ipiv, log_abs_pf, sign, s);
+    if (e != hipSuccess)
+        return device_error(e, "pfaffian launch");
     tm_end(ti, s, 0.0);
     return SKLTLT_OK;
 }

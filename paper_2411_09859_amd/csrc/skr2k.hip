@@ -220,6 +220,7 @@ hipError_t launch_skr2k(double *A, int lda, int n, int cp, int nq, const FactorW
     const int per_xcd = (ntiles + 7) / 8;
     const int grid = per_xcd * 8;
     const int K = 2 * nq;
+    (void)hipGetLastError(); // report this launch only
     if (precision == 1) {
         hipLaunchKernelGGL(skr2k_kernel<float>, dim3(grid), dim3(256), 0, s, A, lda, n, cp, K,
                            (const float *)ws.uv32, ntiles);

@@ -59,8 +59,10 @@ def tune(count=512, seed=7, verbose=True):
     return table, meas
 
 
-def write_outputs(table, meas):
-    with open(os.path.join(PKG, "tune_batched.json"), "w") as f:
+def write_outputs(table, meas, out_dir=None):
+    jdir = out_dir or PKG
+    hdir = out_dir or os.path.join(PKG, "csrc")
+    with open(os.path.join(jdir, "tune_batched.json"), "w") as f:
         json.dump({"device": "MI355X (gfx950)", "classes": meas}, f, indent=1)
     lines = ["// Panel width of the batched kernel per matrix order, measured on MI355X",
              "// by paper_2411_09859_amd/tune_batched.py (written by the tuner).",
@@ -70,7 +72,7 @@ def write_outputs(table, meas):
              "constexpr BatchedTune kBatchedTune[] = {"]
     lines += [f"    {{{hi}, {bs}}}," for hi, bs in table]
     lines += ["};", "}  // namespace skl", ""]
-    with open(os.path.join(PKG, "csrc", "batched_table.h"), "w") as f:
+    with open(os.path.join(hdir, "batched_table.h"), "w") as f:
         f.write("\n".join(lines))
 
 
@@ -78,11 +80,12 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--count", type=int, default=512)
     ap.add_argument("--no-write", action="store_true")
+    ap.add_argument("--out-dir", default=None, help="write both files here instead")
     args = ap.parse_args()
     binding.lib()
     table, meas = tune(args.count)
     if not args.no_write:
-        write_outputs(table, meas)
+        write_outputs(table, meas, args.out_dir)
     print(json.dumps({"table": table}))
 
 
