@@ -90,7 +90,9 @@ def test_known_factors_recovered(n):
     """A = L0 T0 L0^T with L0 e_0 = e_0 and |L0| <= 1/2: partial pivoting makes
     no swap and the factors are recovered (uniqueness, Sec. 3.2).  The
     off-diagonal scale shrinks like 1/sqrt(n) so that L0 stays well
-    conditioned and the recovery error stays at rounding level."""
+    conditioned; at these orders |t| in [1, 2] keeps the forward error at
+    rounding level (at orders in the thousands the ratios |t[a+1]/t[a]|
+    compound and |t| must be nearly constant instead)."""
     rng = np.random.default_rng(100 + n)
     scale = 0.5 * min(1.0, 4.0 / np.sqrt(n))
     L0 = np.eye(n)
