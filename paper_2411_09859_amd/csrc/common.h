@@ -13,17 +13,20 @@ constexpr int kMaxPanelGroups = 1024; // slot array capacity per parity
 constexpr int kMaxBlock = 256;       // largest supported panel width
 constexpr size_t kAlign = 256;
 
-// One record per panel workgroup and step parity, as eight 8-byte words,
-// each with the 32-bit step stamp in its high half: [0,1] the candidate value
-// x[idx] (high and low halves of the double), [2] the candidate row index,
-// [3] its physical row in the row mirror; the group owning row r = c+1 also
-// writes [4,5] x[r] and [6] the physical row of r.
+// One record per panel workgroup and step parity: eight 8-byte words, of
+// which the panel uses three, each carrying the step stamp: [0] and [1] the
+// high and low halves of the candidate value under a 32-bit stamp, [2] a
+// 16-bit stamp, the candidate row relative to the panel base and its
+// register row (24 bits each).
 struct alignas(64) Slot {
     unsigned long long w[8];
 };
 
 // Device workspace of skltlt_factor, carved from the caller's buffer.
 struct FactorWs {
+    double *W[2];      // full skew copies of the trailing matrix (ping-pong), ld = ldw
+    int ldw;
+    int *perm;         // panel permutation: perm[pos] = row at the panel start
     double *mirror;    // physical panel rows, row-major, ld = ldm
     int ldm;
     double *lcar;      // carried L column (n doubles)
@@ -47,18 +50,35 @@ struct PanelShape {
     size_t lds;
 };
 PanelShape panel_shape(int n, int k0, int b, int max_groups);
-hipError_t launch_panel(double *A, int lda, int n, int k0, int nb, int b,
+// W: the full skew trailing matrix as of the panel start (read only).
+hipError_t launch_panel(double *A, int lda, const double *W, int n, int k0, int nb, int b,
                         double *t, int *ipiv, const FactorWs &ws, int want32,
                         const PanelShape &sh, hipStream_t s);
 
-hipError_t launch_skr2k(double *A, int lda, int n, int cp, int nq,
+// Wn[i][j] = Wc[perm[i]][perm[j]] - (U V^T - V U^T)[i][j] for i != j >= cp.
+hipError_t launch_skr2k(const double *Wc, double *Wn, int n, int cp, int nq,
                         const FactorWs &ws, int precision, hipStream_t s);
+
+// W = the full skew matrix whose strict lower triangle is A's.
+hipError_t launch_init_full(const double *A, int lda, int n, double *W, int ldw, hipStream_t s);
 
 hipError_t launch_finalize(double *A, int lda, int n, int b, const int *ipiv,
                            const FactorWs &ws, hipStream_t s);
 
 hipError_t launch_pfaffian(int n, const double *t, const int *ipiv,
                            double *log_abs_pf, int *sign, hipStream_t s);
+
+// Lower-triangle tile enumeration: tau = I (I + 1) / 2 + J with 0 <= J <= I.
+__device__ __forceinline__ void tile_of(int tau, int *ti, int *tj)
+{
+    int I = (int)((sqrtf(8.0f * (float)tau + 1.0f) - 1.0f) * 0.5f);
+    while ((I + 1) * (I + 2) / 2 <= tau)
+        ++I;
+    while (I * (I + 1) / 2 > tau)
+        --I;
+    *ti = I;
+    *tj = tau - I * (I + 1) / 2;
+}
 
 int device_cu_count();
 // Records the HIP error behind an SKLTLT_EDEVICE; returns SKLTLT_EDEVICE.

@@ -20,22 +20,27 @@
 //      redundantly by every group from the same data);
 //   2. x_i = Y[i, c] - L[i, panel] . h for owned rows i >= r, where Y is the
 //      trailing matrix as of the panel start with this panel's symmetric
-//      exchanges applied in place;
+//      exchanges applied;
 //   3. argmax of |x_i| (first index on ties) over the group;
 //   4. with several groups: each group publishes its candidate in a slot of
 //      self-validating words (every 8-byte word carries the step stamp) and
 //      polls all slots; every group reduces them to the same pivot p;
-//   5. exchange rows/columns r <-> p of the trailing matrix (lower storage
-//      rule, one element per row), relabel the register rows of r and p,
-//      and form the new column of L, l = x / tau (0 if tau = 0).
-// An exchange of rows r and p never moves register data: the two register
-// rows swap the matrix rows they stand for (the one that held r keeps its x
-// and continues as p; the one that held p is row r, final for this panel).
-// Other groups read the pivot row from a row-major mirror in HBM indexed by
-// register row, which is written once per column and never rewritten.
-// Cross-group words (slots, the mirror, the trailing matrix) are relaxed
-// device-scope atomics: coherent across XCDs without L2 write-back or
-// invalidation.
+//   5. exchange rows/columns r <-> p: relabel the register rows of r and p,
+//      load the next column, and form the new column of L, l = x / tau
+//      (0 if tau = 0).
+// The exchanges are never applied to memory here.  A register row always
+// holds the same row of the panel-start matrix Y0 (its "original" row) and
+// only the label it stands for changes: the one that held r continues as p
+// with its x, the one that held p becomes row r, final for this panel.  The
+// trailing matrix is kept in full skew storage (both triangles), so entry
+// (label i, label r) of the exchanged matrix is Y0[orig(i), orig(r)], one
+// coalesced column of Y0 per step.  The skr2k kernel applies the panel's
+// permutation when it forms the next trailing matrix.  The panel writes
+// nothing but its outputs: L, t, pivots, the permutation, the operands.
+// Other groups read the pivot row of L from a row-major mirror in HBM indexed
+// by register row, which is written once per column and never rewritten.
+// Cross-group words (slots, the mirror) are relaxed device-scope atomics:
+// coherent across XCDs without L2 write-back or invalidation.
 #include "common.h"
 
 #include <climits>
@@ -95,14 +100,20 @@ constexpr long kSpinLimit = 1L << 20;
 
 template <int NT, int TPR, int kNS>
 __global__ __launch_bounds__(NT) void panel_kernel(
-    double *__restrict__ A, int lda, int n, int k0, int nb, int b,
-    double *__restrict__ t, int *__restrict__ ipiv, double *__restrict__ mirror,
+    double *__restrict__ A, int lda, const double *__restrict__ W, int ldw, int n, int k0,
+    int nb, int b, double *__restrict__ t, int *__restrict__ ipiv, int *__restrict__ perm,
+    double *__restrict__ mirror,
     int ldm, double *__restrict__ lcar, double *__restrict__ uv,
     float *__restrict__ uv32, int want32, Slot *__restrict__ slots, int G, int one_xcd)
 {
     constexpr int R = NT / TPR;
     constexpr int NW = NT / 64;
-    constexpr int NA = kNS * TPR; // columns representable per row
+    // New columns are inserted into a ring of kRing registers; a full ring
+    // group is flushed into Lreg once (kRing * TPR column steps).  Inserting
+    // into Lreg directly needs a select over every slot at every step.
+    constexpr int kRing = 8;
+    constexpr int kNSR = ((kNS + kRing - 1) / kRing) * kRing;
+    constexpr int NA = kNSR * TPR; // columns addressable through the ring
     extern __shared__ double stage[]; // R x 34, epilogue only
 
     __shared__ double hv[NA];
@@ -133,6 +144,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     const int lr = tid / TPR;       // register row of this thread
     const int sub = tid - lr * TPR; // column class of this thread
     const int phys = w * R + lr;    // its row in the mirror (fixed)
+    const int orow = base + phys;   // its row of the panel-start matrix (fixed)
     const bool multi = (G > 1);
     const bool local = (one_xcd != 0);
     unsigned long long *sl64 = (unsigned long long *)slots;
@@ -141,13 +153,26 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     // relabels the two register rows instead of moving their data: the one
     // that held row r now holds row p and keeps its x, the one that held
     // row p becomes row r, which is final for this panel.
-    int pos = base + phys;
-    const bool exists = (pos < n);
+    int pos = orow;
+    const bool exists = (orow < n);
 
-    double Lreg[kNS];
+    double Lreg[kNS];   // slots of flushed ring groups (slot q: column sub + TPR q)
+    double Lnew[kRing]; // slots g kRing .. g kRing + kRing - 1 of the current group g
 #pragma unroll
     for (int q = 0; q < kNS; ++q)
         Lreg[q] = 0.0;
+#pragma unroll
+    for (int i = 0; i < kRing; ++i)
+        Lnew[i] = 0.0;
+    // copy the ring into ring group g of Lreg and clear it (g uniform)
+    auto flush_ring = [&](int g) {
+#pragma unroll
+        for (int q = 0; q < kNS; ++q)
+            Lreg[q] = (q / kRing == g) ? Lnew[q % kRing] : Lreg[q];
+#pragma unroll
+        for (int i = 0; i < kRing; ++i)
+            Lnew[i] = 0.0;
+    };
 
     // ---- panel start: carried column (column 0 of the panel) and the first
     //      column of Y
@@ -158,43 +183,64 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     }
     if (exists && sub == 0) {
         const double l0 = (k0 == 0) ? 0.0 : lcar[pos];
-        Lreg[0] = l0;
+        Lnew[0] = l0;
         if (multi)
             st_xcd(&mirror[(size_t)phys * ldm], l0, local);
-        ycol = ld_dev(&A[(size_t)k0 * lda + pos]);
+        ycol = W[(size_t)k0 * ldw + orow];
     }
     ycol = __shfl(ycol, lane & ~(TPR - 1), 64);
     if (tid == 0)
         bc_fail = 0;
     __syncthreads();
 
+    // Broadcast the step's pivot through LDS; an index that does not name an
+    // existing candidate row can only follow a failed wait and poisons the
+    // result (tau = NaN) while keeping every later access in range.
+    int r_cur = 0;
+    auto set_pivot = [&](double v, int idx, int ph) {
+        if (idx < r_cur || idx >= n || ph < 0 || ph >= G * R || base + ph >= n) {
+            bc_p = r_cur;
+            bc_physp = 0;
+            bc_fail = 1;
+        } else {
+            bc_p = idx;
+            bc_physp = ph;
+        }
+        bc_tau = v;
+    };
+
     for (int j = 0; j < nb; ++j) {
         const int c = k0 + j;
         const int r = c + 1;
+        r_cur = r;
         const int par = c & 1;
-        const bool last = (r == k0 + nb);
         const unsigned stamp = (unsigned)(c + 1);
 
         // 1. h[a] = sum_b T[a][b] L[c][b] over the panel columns a, b in 0..j,
         //    T tridiagonal with T[a+1][a] = t_a, T[a][a+1] = -t_a, L[c][j] = 1.
-        //    Entries of h beyond j stay zero.
-        if (tid <= j) {
-            const int a = tid;
-            double v = 0.0;
-            if (a + 1 <= j)
-                v -= tl[a] * ((a + 1 < j) ? hrow[a + 1] : 1.0);
-            if (a >= 1)
-                v += tl[a - 1] * hrow[a - 1];
-            hv[a] = v;
+        //    Entries of h beyond j stay zero.  With several groups h is
+        //    formed at the end of the previous step (no barrier here).
+        if (!multi) {
+            if (tid <= j) {
+                const int a = tid;
+                double v = 0.0;
+                if (a + 1 <= j)
+                    v -= tl[a] * ((a + 1 < j) ? hrow[a + 1] : 1.0);
+                if (a >= 1)
+                    v += tl[a - 1] * hrow[a - 1];
+                hv[a] = v;
+            }
+            __syncthreads();
         }
-        __syncthreads();
 
-        // 2. x_i = Y[i, c] - sum_a L[i][a] h[a] over the filled columns.
+        // 2. x_i = Y[i, c] - sum_a L[i][a] h[a] over the filled columns:
+        //    flushed ring groups from Lreg, the current group from the ring.
+        const int gr = (j / TPR) / kRing; // ring group of column j (uniform)
         const bool cand = exists && (pos >= r);
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
         for (int q = 0; q < kNS; q += 4) {
-            if (q * TPR <= j) { // uniform: only the filled columns 0..j
+            if (q < gr * kRing) { // uniform
                 s0 += Lreg[q] * hv[sub + TPR * q];
                 if (q + 1 < kNS)
                     s1 += Lreg[q + 1] * hv[sub + TPR * (q + 1)];
@@ -203,6 +249,11 @@ __global__ __launch_bounds__(NT) void panel_kernel(
                 if (q + 3 < kNS)
                     s3 += Lreg[q + 3] * hv[sub + TPR * (q + 3)];
             }
+        }
+#pragma unroll
+        for (int i = 0; i < kRing; i += 2) {
+            s0 += Lnew[i] * hv[sub + TPR * (gr * kRing + i)];
+            s1 += Lnew[i + 1] * hv[sub + TPR * (gr * kRing + i + 1)];
         }
         double s = (s0 + s1) + (s2 + s3);
 #pragma unroll
@@ -234,8 +285,8 @@ __global__ __launch_bounds__(NT) void panel_kernel(
             red_i[wave] = ci;
             red_ph[wave] = cph;
         }
-        // this wave's exchange and mirror stores of the previous step must be
-        // complete before this step's slot is published
+        // this wave's mirror stores of the previous step must be complete
+        // before this step's slot is published
         if (multi)
             wait_vm();
         __syncthreads();
@@ -264,9 +315,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(
                 st_xcd(&wv[2], ((unsigned long long)s16 << 48) |
                                    ((unsigned long long)ib << 24) | (unsigned)bph, local);
             } else {
-                bc_tau = bv;
-                bc_p = bi;
-                bc_physp = bph;
+                set_pivot(bv, bi, bph);
             }
         }
 
@@ -304,49 +353,57 @@ __global__ __launch_bounds__(NT) void panel_kernel(
                     gph = (int)(w2 & 0xffffffu);
                 }
             }
-            // reduce the candidates held by the waves that polled
-            if (wave * 64 < G) {
+            if (G <= 64) {
+                // every candidate is in wave 0: reduce there, no barrier
+                if (wave == 0) {
 #pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) {
-                    const double ov = __shfl_xor(gv, off, 64);
-                    const int oi = __shfl_xor(gi, off, 64);
-                    const int oph = __shfl_xor(gph, off, 64);
-                    if (beats(ov, oi, gv, gi)) {
-                        gv = ov;
-                        gi = oi;
-                        gph = oph;
+                    for (int off = 32; off >= 1; off >>= 1) {
+                        const double ov = __shfl_xor(gv, off, 64);
+                        const int oi = __shfl_xor(gi, off, 64);
+                        const int oph = __shfl_xor(gph, off, 64);
+                        if (beats(ov, oi, gv, gi)) {
+                            gv = ov;
+                            gi = oi;
+                            gph = oph;
+                        }
+                    }
+                    if (lane == 0)
+                        set_pivot(gv, gi, gph);
+                }
+            } else {
+                // reduce the candidates held by the waves that polled
+                if (wave * 64 < G) {
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1) {
+                        const double ov = __shfl_xor(gv, off, 64);
+                        const int oi = __shfl_xor(gi, off, 64);
+                        const int oph = __shfl_xor(gph, off, 64);
+                        if (beats(ov, oi, gv, gi)) {
+                            gv = ov;
+                            gi = oi;
+                            gph = oph;
+                        }
                     }
                 }
-            }
-            __syncthreads(); // red_* of step 3 were consumed by thread 0
-            if (lane == 0 && wave * 64 < G) {
-                red_v[wave] = gv;
-                red_i[wave] = gi;
-                red_ph[wave] = gph;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                double bv = red_v[0];
-                int bi = red_i[0], bph = red_ph[0];
-                for (int q = 1; q * 64 < G; ++q) {
-                    if (beats(red_v[q], red_i[q], bv, bi)) {
-                        bv = red_v[q];
-                        bi = red_i[q];
-                        bph = red_ph[q];
-                    }
+                __syncthreads(); // red_* of step 3 were consumed by thread 0
+                if (lane == 0 && wave * 64 < G) {
+                    red_v[wave] = gv;
+                    red_i[wave] = gi;
+                    red_ph[wave] = gph;
                 }
-                bc_tau = bv;
-                bc_p = bi;
-                bc_physp = bph;
-            }
-        }
-        __syncthreads();
-        if (tid == 0) {
-            const int bi = bc_p, bph = bc_physp;
-            if (bi < r || bi >= n || bph < 0 || bph >= G * R) { // only after a failed wait
-                bc_p = r;
-                bc_physp = 0;
-                bc_fail = 1;
+                __syncthreads();
+                if (tid == 0) {
+                    double bv = red_v[0];
+                    int bi = red_i[0], bph = red_ph[0];
+                    for (int q = 1; q * 64 < G; ++q) {
+                        if (beats(red_v[q], red_i[q], bv, bi)) {
+                            bv = red_v[q];
+                            bi = red_i[q];
+                            bph = red_ph[q];
+                        }
+                    }
+                    set_pivot(bv, bi, bph);
+                }
             }
         }
         __syncthreads();
@@ -356,13 +413,27 @@ __global__ __launch_bounds__(NT) void panel_kernel(
 
         // 5a. the pivot row of L (row p before the exchange): it is the
         //     previous row for the next step's h.
+        //     With several groups, thread a forms h[a] of the next step from
+        //     entries a-1 and a+1 of that row (read from the mirror) and t.
+        double hn = 0.0;
         if (multi) {
-            if (tid <= j)
-                hrow[tid] = ld_dev(&mirror[(size_t)physp * ldm + tid]);
+            if (tid <= j + 1 && j + 1 < nb) {
+                const int a = tid;
+                const double *mrow = mirror + (size_t)physp * ldm;
+                if (a + 1 <= j + 1) {
+                    const double up = (a + 1 < j + 1) ? ld_dev(&mrow[a + 1]) : 1.0;
+                    hn -= ((a == j) ? tau : tl[a]) * up;
+                }
+                if (a >= 1)
+                    hn += ((a - 1 == j) ? tau : tl[a - 1]) * ld_dev(&mrow[a - 1]);
+            }
         } else if (exists && pos == p) {
 #pragma unroll
             for (int q = 0; q < kNS; ++q)
                 hrow[sub + TPR * q] = Lreg[q];
+#pragma unroll
+            for (int i = 0; i < kRing; ++i)
+                hrow[sub + TPR * (gr * kRing + i)] = Lnew[i];
         }
 
         // 5b. relabel: the register row of r now holds p, the one of p holds r.
@@ -373,61 +444,42 @@ __global__ __launch_bounds__(NT) void panel_kernel(
                 pos = r;
         }
 
-        // 5c. symmetric exchange r <-> p of the trailing matrix in lower
-        //     storage, one row i > r per register row; ycol becomes Y'[i, r].
-        if (exists && sub == 0 && pos > r) {
-            double *colr = A + (size_t)r * lda;
-            double ynew;
-            if (p == r) {
-                ynew = ld_dev(&colr[pos]);
-            } else if (pos > p) {
-                double *colp = A + (size_t)p * lda;
-                const double av = ld_dev(&colr[pos]);
-                const double bvv = ld_dev(&colp[pos]);
-                st_xcd(&colp[pos], av, local);
-                if (last)
-                    st_xcd(&colr[pos], bvv, local);
-                ynew = bvv;
-            } else if (pos < p) {
-                double *pi = A + (size_t)pos * lda + p;
-                const double av = ld_dev(&colr[pos]);
-                const double bvv = ld_dev(pi);
-                st_xcd(pi, -av, local);
-                if (last)
-                    st_xcd(&colr[pos], -bvv, local);
-                ynew = -bvv;
-            } else {
-                const double av = ld_dev(&colr[p]);
-                if (last)
-                    st_xcd(&colr[p], -av, local);
-                ynew = -av;
-            }
-            ycol = ynew;
-        }
+        // 5c. next column: entry (label i, label r) of the exchanged matrix is
+        //     Y0[orig(i), orig(r)], and orig(r) is the original row of the
+        //     register row that held p.  W is not written during the panel.
+        if (exists && sub == 0 && pos > r)
+            ycol = W[(size_t)(base + physp) * ldw + orow];
         ycol = __shfl(ycol, lane & ~(TPR - 1), 64);
 
         // 5d. new column of L: l_i = x_i / tau for rows i > r (each register
         //     row keeps its own x); row r gets its unit diagonal.
+        //     Column j+1 sits in ring group (j+1)/TPR/kRing; when that is a
+        //     new group, the finished one is flushed first (every thread).
+        const int a1 = j + 1;
+        if (((a1 / TPR) / kRing) != gr)
+            flush_ring(gr);
         if (exists && pos >= r) {
-            const int a1 = j + 1;
             const double l = (pos == r) ? 1.0 : ((tau != 0.0) ? xv / tau : 0.0);
             if (sub == a1 % TPR) {
-                // select into every slot (keeps Lreg in registers: an indexed
+                // select into the ring (keeps it in registers: an indexed
                 // store would move the array to scratch memory)
-                const int slot = a1 / TPR;
+                const int slot = (a1 / TPR) % kRing;
 #pragma unroll
-                for (int q = 0; q < kNS; ++q)
-                    Lreg[q] = (q == slot) ? l : Lreg[q];
+                for (int i = 0; i < kRing; ++i)
+                    Lnew[i] = (i == slot) ? l : Lnew[i];
                 if (multi && pos > r)
                     st_xcd(&mirror[(size_t)phys * ldm + a1], l, local);
             }
         }
+        if (multi && tid <= j + 1 && j + 1 < nb)
+            hv[tid] = hn;
         if (tid == 0) {
             tl[j] = tau;
             pl[j] = p;
         }
         __syncthreads();
     }
+    flush_ring((nb / TPR) / kRing); // the group of the last column
 
     // ---- panel end: pivots and t, L into A (shifted one column left), t on
     //      the subdiagonal, the carried column, and the skr2k operands.
@@ -450,8 +502,11 @@ __global__ __launch_bounds__(NT) void panel_kernel(
                 lcar[pos] = Lreg[q];
         }
     }
-    if (sub == 0)
+    if (sub == 0) {
         posl[lr] = exists ? pos : -1;
+        if (exists)
+            perm[pos] = orow;
+    }
     if (cp < n - 1) {
         // U_q = -t_2q L[:,2q] + t_2q+1 L[:,2q+2], V_q = L[:,2q+1] for the rows
         // >= cp, staged in LDS 32 columns at a time
@@ -529,10 +584,12 @@ PanelShape panel_shape(int n, int k0, int b, int max_groups)
 }
 
 template <int TPR, int NS>
-static hipError_t launch_t(double *A, int lda, int n, int k0, int nb, int b, double *t,
-                           int *ipiv, const FactorWs &ws, int want32, const PanelShape &sh,
-                           hipStream_t s)
+static hipError_t launch_t(double *A, int lda, const double *W, int n, int k0, int nb, int b,
+                           double *t, int *ipiv, const FactorWs &ws, int want32,
+                           const PanelShape &sh, hipStream_t s)
 {
+    int ldw = ws.ldw;
+    int *perm = ws.perm;
     double *mirror = ws.mirror;
     int ldm = ws.ldm;
     double *lcar = ws.lcar;
@@ -541,8 +598,8 @@ static hipError_t launch_t(double *A, int lda, int n, int k0, int nb, int b, dou
     Slot *slots = ws.slots;
     int G = sh.G;
     int one_xcd = (G > 1 && G <= kXcdCUs) ? 1 : 0;
-    void *args[] = {&A, &lda, &n, &k0, &nb, &b, &t, &ipiv, &mirror, &ldm, &lcar,
-                    &uv, &uv32, &want32, &slots, &G, &one_xcd};
+    void *args[] = {&A, &lda, &W, &ldw, &n, &k0, &nb, &b, &t, &ipiv, &perm, &mirror, &ldm,
+                    &lcar, &uv, &uv32, &want32, &slots, &G, &one_xcd};
     const void *fn = (const void *)panel_kernel<kNT, TPR, NS>;
     if (G == 1) // no cross-group exchange: an ordinary launch
         return hipLaunchKernel(fn, dim3(1), dim3(kNT), args, (unsigned)sh.lds, s);
@@ -550,13 +607,14 @@ static hipError_t launch_t(double *A, int lda, int n, int k0, int nb, int b, dou
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kNT), args, (unsigned)sh.lds, s);
 }
 
-hipError_t launch_panel(double *A, int lda, int n, int k0, int nb, int b, double *t, int *ipiv,
-                        const FactorWs &ws, int want32, const PanelShape &sh, hipStream_t s)
+hipError_t launch_panel(double *A, int lda, const double *W, int n, int k0, int nb, int b,
+                        double *t, int *ipiv, const FactorWs &ws, int want32,
+                        const PanelShape &sh, hipStream_t s)
 {
     switch (shape_id(b)) {
-    case 0: return launch_t<1, 65>(A, lda, n, k0, nb, b, t, ipiv, ws, want32, sh, s);
-    case 1: return launch_t<2, 65>(A, lda, n, k0, nb, b, t, ipiv, ws, want32, sh, s);
-    default: return launch_t<4, 65>(A, lda, n, k0, nb, b, t, ipiv, ws, want32, sh, s);
+    case 0: return launch_t<1, 65>(A, lda, W, n, k0, nb, b, t, ipiv, ws, want32, sh, s);
+    case 1: return launch_t<2, 65>(A, lda, W, n, k0, nb, b, t, ipiv, ws, want32, sh, s);
+    default: return launch_t<4, 65>(A, lda, W, n, k0, nb, b, t, ipiv, ws, want32, sh, s);
     }
 }
 

@@ -3,10 +3,12 @@
 //
 // Sequence per call (paper arXiv 2411.09859, Sec. 3.6.3 fused blocked
 // right-looking algorithm with the pivoting of Sec. 3.7.3, code of Sec. 4.2):
-//   for each panel of b columns: panel kernel (pivot search, exchanges,
-//   L columns, t, operands U and V), then the skr2k kernel on the trailing
-//   lower triangle; after the last panel: the deferred row exchanges of the
-//   earlier L columns.  Pivot choices stay on the device; the host never
+//   copy the input into full skew storage W0; for each panel of b columns:
+//   panel kernel (pivot search, L columns, t, permutation, operands U and
+//   V; reads W only), then the skr2k kernel, which applies the panel's
+//   permutation and the update while writing the next trailing matrix into
+//   the other W buffer; after the last panel: the deferred row exchanges of
+//   the earlier L columns.  Pivot choices stay on the device; the host never
 //   synchronizes with the stream.
 #include "../../include/skltlt.h"
 #include "common.h"
@@ -36,8 +38,14 @@ int device_cu_count()
     return cus;
 }
 
-// Workspace: mirror (n x (b+2) fp64, row-major), carried column (n),
-// operands [U|V|-V|U] (n x 4k fp64) and their fp32 copy, slots, gather maps.
+// Leading dimension of the W buffers: n rounded up to 32 doubles plus 32, so
+// that columns do not sit at a power-of-two stride.
+static int work_ld(int n) { return ((n + 31) / 32) * 32 + 32; }
+
+// Workspace: two full skew work matrices (n x ldw fp64 each), the panel
+// permutation (n), mirror ((n + 512) x (b+2) fp64, row-major), carried
+// column (n), operands [U|V|-V|U] (n x 4k fp64) and their fp32 copy, slots,
+// gather maps.
 size_t factor_ws_layout(int n, int b, FactorWs *ws, char *base)
 {
     const int nq = (b + 1) / 2;
@@ -50,6 +58,10 @@ size_t factor_ws_layout(int n, int b, FactorWs *ws, char *base)
         return base ? base + o : nullptr;
     };
     FactorWs w{};
+    w.ldw = work_ld(n);
+    w.W[0] = (double *)take(sizeof(double) * nn * (size_t)w.ldw);
+    w.W[1] = (double *)take(sizeof(double) * nn * (size_t)w.ldw);
+    w.perm = (int *)take(sizeof(int) * nn);
     w.ldm = b + 2;
     w.mirror = (double *)take(sizeof(double) * (nn + 512) * (size_t)(b + 2));
     w.lcar = (double *)take(sizeof(double) * nn);
@@ -168,6 +180,8 @@ static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int bloc
         if (n > 1 && (e = launch_fill_zero(ws.slots, sizeof(Slot) * 2 * kMaxPanelGroups, s)) !=
                          hipSuccess)
             return device_error(e, "clear slots");
+        if (n > 1 && (e = launch_init_full(A, lda, n, ws.W[0], ws.ldw, s)) != hipSuccess)
+            return device_error(e, "full copy");
         tm_end(ti, s, 0.0);
     }
     if (n == 1)
@@ -180,13 +194,14 @@ static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int bloc
     if (maxg <= 0)
         return device_error(hipErrorInvalidValue, "panel occupancy query");
 
+    int cur = 0; // W buffer holding the current trailing matrix
     for (int k0 = 0; k0 < n - 1; k0 += b) {
         const int nb = (b < n - 1 - k0) ? b : (n - 1 - k0);
         PanelShape sh = panel_shape(n, k0, b, maxg);
         if (sh.lds > kLdsCap || sh.G > maxg || 8L * sh.G > 8L * maxg)
             return SKLTLT_ENOTSUP;
         int ti = tm_begin(SKLTLT_K_PANEL, s);
-        hipError_t e = launch_panel(A, lda, n, k0, nb, b, t, ipiv, ws, want32, sh, s);
+        hipError_t e = launch_panel(A, lda, ws.W[cur], n, k0, nb, b, t, ipiv, ws, want32, sh, s);
         if (e != hipSuccess)
             return device_error(e, "panel launch");
         tm_end(ti, s, 0.0);
@@ -195,8 +210,10 @@ static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int bloc
             const int nq = (nb + 1) / 2;
             const double m = (double)(n - cp);
             ti = tm_begin(SKLTLT_K_SKR2K, s);
-            if ((e = launch_skr2k(A, lda, n, cp, nq, ws, precision, s)) != hipSuccess)
+            if ((e = launch_skr2k(ws.W[cur], ws.W[cur ^ 1], n, cp, nq, ws, precision, s)) !=
+                hipSuccess)
                 return device_error(e, "skr2k launch");
+            cur ^= 1;
             // strict lower triangle of the m x m trailing block, K = 2*nq
             tm_end(ti, s, m * (m - 1.0) * 0.5 * 2.0 * (2.0 * nq));
         }

@@ -14,11 +14,20 @@
 // GEMM with K = 2k restricted to the strict lower triangle of the trailing
 // block (rows and columns cp..n-1, the first column included).
 //
+// The trailing matrix is held in full skew storage, and the panel does not
+// apply its row/column exchanges to it; this kernel does.  It reads
+// C[i][j] = Wc[perm[i]][perm[j]] (perm: row of the panel-start matrix that
+// position i holds after the panel's exchanges) and writes the updated entry
+// and its negation to (i, j) and (j, i) of the other buffer Wn, so each
+// panel's permutation costs no extra pass over the matrix.
+//
 // Tiling: a 128x128 output tile per 256-thread workgroup, four waves of
 // 64x64, each a 4x4 grid of 16x16 MFMA blocks.  The MFMA computes the
 // transposed tile, D[j][i], so that each lane's four accumulator values lie
 // in four columns at one row i and sixteen consecutive lanes cover sixteen
-// consecutive rows: loads and stores of C are 128-byte segments.  Tiles are
+// consecutive rows: loads of C and stores of the lower entries are 128-byte
+// segments (the mirrored upper stores are 32-byte pieces of lines that the
+// L2 completes before writing them back).  Tiles are
 // enumerated over the lower triangle only; a diagonal tile skips the wave
 // whose 64x64 quarter lies strictly above the diagonal and masks the rest.
 // Consecutive tile indices go to one XCD (workgroup ids are dealt to the 8
@@ -30,6 +39,7 @@ namespace skl {
 constexpr int TM = 128;    // tile rows (i) and columns (j)
 constexpr int TMP = 144;   // padded LDS row (k-rows 1152 B apart: banks shift by 128 B)
 constexpr int KC = 16;     // K chunk staged in LDS
+constexpr int TRS = 66;    // LDS row of the epilogue transpose (64 + 2: spreads banks)
 
 template <typename T> struct MfmaT;
 // Output layout of the 16x16 MFMA result held by lane l (value q of 4),
@@ -52,28 +62,25 @@ template <> struct MfmaT<float> {
     static __device__ __forceinline__ int drow(int lk, int q) { return 4 * lk + q; }
 };
 
-__device__ __forceinline__ void tile_of(int tau, int *ti, int *tj)
-{
-    // tau = I*(I+1)/2 + J with 0 <= J <= I
-    int I = (int)((sqrtf(8.0f * (float)tau + 1.0f) - 1.0f) * 0.5f);
-    while ((I + 1) * (I + 2) / 2 <= tau)
-        ++I;
-    while (I * (I + 1) / 2 > tau)
-        --I;
-    *ti = I;
-    *tj = tau - I * (I + 1) / 2;
-}
-
 template <typename T>
-__global__ __launch_bounds__(256, 2) void skr2k_kernel(double *__restrict__ A, int lda, int n,
+__global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict__ Wc,
+                                                       double *__restrict__ Wn, int ldw,
+                                                       const int *__restrict__ perm, int n,
                                                        int cp, int K, const T *__restrict__ uv,
                                                        int ntiles)
 {
     typedef typename MfmaT<T>::acc4 acc4;
-    // double-buffered operand chunks, k-major, rows padded so that the four
-    // k-rows read by one fragment load fall in different LDS banks
-    __shared__ T sI[2][KC][TMP]; // [U|V] rows i
-    __shared__ T sJ[2][KC][TMP]; // [-V|U] rows j
+    // LDS: double-buffered operand chunks during the K loop, k-major, rows
+    // padded so that the four k-rows read by one fragment load fall in
+    // different LDS banks; afterwards each wave reuses 16 x TRS doubles of
+    // the same space to transpose its mirrored (upper) stores.
+    constexpr size_t kOpBytes = sizeof(T) * 2 * KC * TMP;
+    constexpr size_t kTrBytes = sizeof(double) * 4 * 16 * TRS;
+    constexpr size_t kLds = (2 * kOpBytes > kTrBytes) ? 2 * kOpBytes : kTrBytes;
+    __shared__ __attribute__((aligned(16))) char smem[kLds];
+    T(*sI)[KC][TMP] = reinterpret_cast<T(*)[KC][TMP]>(smem);            // [U|V] rows i
+    T(*sJ)[KC][TMP] = reinterpret_cast<T(*)[KC][TMP]>(smem + kOpBytes); // [-V|U] rows j
+    __shared__ int sPi[TM], sPj[TM]; // source rows of the tile's rows and columns
 
     // XCD-grouped tile order
     const int nwg = gridDim.x;
@@ -98,26 +105,19 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(double *__restrict__ A, i
     const int lrow = lane & 15; // row inside a 16-block
     const int lk = lane >> 4;   // k inside a 4-step, or row group of D
 
-    // Accumulators.  FP64: start from the C tile itself (loads issued first so
-    // their latency overlaps the operand staging); FP32: start from zero and
-    // add the fp32 product to C in fp64 at the end.
-    acc4 acc[4][4];
-    constexpr bool kF64 = sizeof(T) == 8;
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
-        const int gi = ib + bi * 16 + lrow;
-#pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int gj = jb + bj * 16 + MfmaT<T>::drow(lk, q);
-                T v = 0;
-                if (kF64 && active && gi < n && gj < gi)
-                    v = (T)A[(size_t)gj * lda + gi];
-                acc[bi][bj][q] = v;
-            }
-        }
+    // Source rows of the tile's rows and columns (loaded first, their latency
+    // overlaps the first operand chunk).
+    if (tid < TM) {
+        const int g = i0 + tid;
+        sPi[tid] = (g < n) ? perm[g] : 0;
+    } else {
+        const int g = j0 + tid - TM;
+        sPj[tid - TM] = (g < n) ? perm[g] : 0;
     }
+    constexpr bool kF64 = sizeof(T) == 8;
+    auto csrc = [&](int gi, int gj) -> const double * {
+        return Wc + (size_t)sPj[gj - j0] * ldw + sPi[gi - i0];
+    };
 
     const T *opI = uv;                 // columns [0, K)
     const T *opJ = uv + (size_t)K * n; // columns [K, 2K)
@@ -157,6 +157,25 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(double *__restrict__ A, i
     if (nk > 1)
         load_chunk(1);
     __syncthreads();
+
+    // Accumulators.  FP64: start from the (permuted) C tile; FP32: start from
+    // zero and add the fp32 product to C in fp64 at the end.
+    acc4 acc[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+        const int gi = ib + bi * 16 + lrow;
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gj = jb + bj * 16 + MfmaT<T>::drow(lk, q);
+                T v = 0;
+                if (kF64 && active && gi < n && gj < gi)
+                    v = (T)*csrc(gi, gj);
+                acc[bi][bj][q] = v;
+            }
+        }
+    }
     for (int kc = 0; kc < nk; ++kc) {
         const int cur = kc & 1;
         if (kc + 1 < nk) {
@@ -186,31 +205,50 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(double *__restrict__ A, i
     if (!active)
         return;
 
-    // D[m][nn] (m = MfmaT::drow(lane/16, q) : column j, nn = lane%16 : row i)
+    // D[m][nn] (m = MfmaT::drow(lane/16, q) : column j, nn = lane%16 : row i).
+    // Lower entries (i, j) go straight out: sixteen lanes write 128
+    // consecutive bytes of column j.  Their negations at (j, i) lie along
+    // column i, so each 16-row block is staged in this wave's LDS rows and
+    // written back one column i at a time, 64 consecutive j per store.
+    double *tr = reinterpret_cast<double *>(smem) + wave * 16 * TRS;
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi) {
         const int gi = ib + bi * 16 + lrow;
-        if (gi >= n)
-            continue;
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int gj = jb + bj * 16 + MfmaT<T>::drow(lk, q);
-                if (gj < gi) {
-                    double *cptr = A + (size_t)gj * lda + gi;
-                    if (kF64)
-                        *cptr = (double)acc[bi][bj][q];
-                    else
-                        *cptr = *cptr + (double)acc[bi][bj][q];
+                const int jl = bj * 16 + MfmaT<T>::drow(lk, q);
+                const int gj = jb + jl;
+                double v = 0.0;
+                if (gi < n && gj < gi) {
+                    v = kF64 ? (double)acc[bi][bj][q] : *csrc(gi, gj) + (double)acc[bi][bj][q];
+                    Wn[(size_t)gj * ldw + gi] = v;
                 }
+                tr[lrow * TRS + jl] = v;
             }
         }
+        // the wave's own LDS writes are visible to its later reads (LDS
+        // instructions of one wave execute in order)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int gj = jb + lane;
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            const int gi2 = ib + bi * 16 + rr;
+            const double v = tr[rr * TRS + lane];
+            if (gi2 < n && gj < gi2)
+                Wn[(size_t)gi2 * ldw + gj] = -v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
-hipError_t launch_skr2k(double *A, int lda, int n, int cp, int nq, const FactorWs &ws,
-                        int precision, hipStream_t s)
+hipError_t launch_skr2k(const double *Wc, double *Wn, int n, int cp, int nq,
+                        const FactorWs &ws, int precision, hipStream_t s)
 {
     const int m = n - cp;
     if (m < 2 || nq <= 0)
@@ -222,11 +260,11 @@ hipError_t launch_skr2k(double *A, int lda, int n, int cp, int nq, const FactorW
     const int K = 2 * nq;
     (void)hipGetLastError(); // report this launch only
     if (precision == 1) {
-        hipLaunchKernelGGL(skr2k_kernel<float>, dim3(grid), dim3(256), 0, s, A, lda, n, cp, K,
-                           (const float *)ws.uv32, ntiles);
+        hipLaunchKernelGGL(skr2k_kernel<float>, dim3(grid), dim3(256), 0, s, Wc, Wn, ws.ldw,
+                           (const int *)ws.perm, n, cp, K, (const float *)ws.uv32, ntiles);
     } else {
-        hipLaunchKernelGGL(skr2k_kernel<double>, dim3(grid), dim3(256), 0, s, A, lda, n, cp, K,
-                           (const double *)ws.uv, ntiles);
+        hipLaunchKernelGGL(skr2k_kernel<double>, dim3(grid), dim3(256), 0, s, Wc, Wn, ws.ldw,
+                           (const int *)ws.perm, n, cp, K, (const double *)ws.uv, ntiles);
     }
     return hipGetLastError();
 }
