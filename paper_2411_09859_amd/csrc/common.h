@@ -11,13 +11,15 @@ namespace skl {
 constexpr int kPanelThreads = 512;   // threads per panel workgroup
 constexpr int kMaxPanelGroups = 1024; // slot array capacity per parity
 constexpr int kMaxBlock = 256;       // largest supported panel width
+// one slot per panel workgroup and step parity
+constexpr int kSlotsPerParity = kMaxPanelGroups;
 constexpr size_t kAlign = 256;
 
-// One record per panel workgroup and step parity: eight 8-byte words, of
-// which the panel uses three, each carrying the step stamp: [0] and [1] the
-// high and low halves of the candidate value under a 32-bit stamp, [2] a
-// 16-bit stamp, the candidate row relative to the panel base and its
-// register row (24 bits each).
+// One record per panel workgroup and step parity, a cache line of its own: eight
+// 8-byte words, of which the panel uses three, each carrying the step stamp:
+// [0] and [1] the high and low halves of the candidate value under a 32-bit
+// stamp, [2] a 16-bit stamp, the candidate row relative to the panel base
+// and its register row (24 bits each).
 struct alignas(64) Slot {
     unsigned long long w[8];
 };

@@ -48,10 +48,51 @@
 namespace skl {
 
 
+// Pivot order: larger |x| wins, the smaller row index on ties (evaluated
+// without branches).
 __device__ __forceinline__ bool beats(double av, int ai, double bv, int bi)
 {
     const double aa = fabs(av), bb = fabs(bv);
-    return (aa > bb) || (aa == bb && ai < bi);
+    return (aa > bb) | ((aa == bb) & (ai < bi));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Wave-wide argmax in the pivot order; every lane receives the winner's
+// (v, idx, ph).  First the largest |v| as its bit pattern (monotone for
+// non-negative doubles, two dwords per exchange), then the lanes holding it
+// are found with a ballot; only an exact tie needs a second pass for the
+// smallest index.  Lanes without a candidate hold v = 0, idx = INT_MAX.
+__device__ __forceinline__ void wave_argmax(double &v, int &idx, int &ph)
+{
+    const unsigned long long key = (unsigned long long)__double_as_longlong(fabs(v));
+    unsigned long long km = key;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(km, off, 64);
+        km = (o > km) ? o : km;
+    }
+    const bool top = (key == km);
+    unsigned long long m = __ballot(top);
+    if (__popcll(m) != 1) {
+        int ci = top ? idx : INT_MAX;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const int o = __shfl_xor(ci, off, 64);
+            ci = (o < ci) ? o : ci;
+        }
+        m = __ballot(top && idx == ci);
+    }
+    const int wl = __ffsll((long long)m) - 1;
+    v = readlane_f64(v, wl);
+    idx = __builtin_amdgcn_readlane(idx, wl);
+    ph = __builtin_amdgcn_readlane(ph, wl);
 }
 
 __device__ __forceinline__ double ld_dev(const double *p)
@@ -59,14 +100,6 @@ __device__ __forceinline__ double ld_dev(const double *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_dev(double *p, double v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long ld_dev(const unsigned long long *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_dev(unsigned long long *p, unsigned long long v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -79,21 +112,10 @@ __device__ __forceinline__ void st_xcd(double *p, double v, bool local)
     else
         st_dev(p, v);
 }
-__device__ __forceinline__ void st_xcd(unsigned long long *p, unsigned long long v, bool local)
-{
-    if (local)
-        *p = v;
-    else
-        st_dev(p, v);
-}
 // Wait until this wave's outstanding memory operations have completed.
 __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-// A slot word: 32-bit step stamp in the high half, 32-bit payload below.
-__device__ __forceinline__ unsigned long long sw(unsigned stamp, unsigned payload)
-{
-    return ((unsigned long long)stamp << 32) | payload;
-}
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // bounded waits: a stuck peer never hangs the GPU (the result is poisoned)
 constexpr long kSpinLimit = 1L << 20;
@@ -126,6 +148,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     __shared__ double bc_tau;
     __shared__ int bc_p, bc_physp, bc_fail;
 
+
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -147,7 +170,6 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     const int orow = base + phys;   // its row of the panel-start matrix (fixed)
     const bool multi = (G > 1);
     const bool local = (one_xcd != 0);
-    unsigned long long *sl64 = (unsigned long long *)slots;
 
     // The matrix row a register row represents.  Exchanging rows r and p
     // relabels the two register rows instead of moving their data: the one
@@ -208,6 +230,71 @@ __global__ __launch_bounds__(NT) void panel_kernel(
         }
         bc_tau = v;
     };
+    // A slot is one 16-byte access.  Each of its four dwords carries the
+    // step stamp (4 bits: a slot is rewritten every second step, so the
+    // stale contents it can hold are one write old) above 28 payload bits:
+    // the candidate value (64 bits), its row relative to the panel base
+    // (24 bits, 0xffffff: none) and its register row (24 bits).  A reader
+    // accepts the slot when all four stamps match, so a read that mixes two
+    // writes is never taken for a complete one.
+    const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)slots, (short)0, (int)(sizeof(Slot) * 2 * kSlotsPerParity), 0x00020000);
+    auto publish_slot = [&](int q, unsigned stamp, double v, int idx, int ph) {
+        const unsigned long long xb = (unsigned long long)__double_as_longlong(v);
+        const unsigned vhi = (unsigned)(xb >> 32), vlo = (unsigned)xb;
+        const unsigned ib = (idx == INT_MAX) ? 0xffffffu : (unsigned)(idx - base);
+        const unsigned st = (stamp & 0xfu) << 28;
+        u32x4 d;
+        d.x = st | (vhi >> 4);
+        d.y = st | ((vhi & 0xfu) << 24) | (vlo >> 8);
+        d.z = st | ((vlo & 0xffu) << 20) | (ib >> 4);
+        d.w = st | ((ib & 0xfu) << 24) | ((unsigned)ph & 0xffffffu);
+        if (local)
+            __builtin_amdgcn_raw_buffer_store_b128(d, srs, q * (int)sizeof(Slot), 0, 0);
+        else // device scope (sc1): visible to other XCDs without an L2 write-back
+            __builtin_amdgcn_raw_buffer_store_b128(d, srs, q * (int)sizeof(Slot), 0, 16);
+    };
+    auto load_slot = [&](int q) {
+        return __builtin_amdgcn_raw_buffer_load_b128(srs, q * (int)sizeof(Slot), 0, 16);
+    };
+    auto slot_ready = [](u32x4 d, unsigned stamp) {
+        const unsigned s4 = stamp & 0xfu;
+        return ((d.x >> 28) == s4) & ((d.y >> 28) == s4) & ((d.z >> 28) == s4) &
+               ((d.w >> 28) == s4);
+    };
+    auto fold_slot = [&](u32x4 d, double &gv, int &gi, int &gph) {
+        const unsigned vhi = ((d.x & 0x0fffffffu) << 4) | ((d.y >> 24) & 0xfu);
+        const unsigned vlo = ((d.y & 0x00ffffffu) << 8) | ((d.z >> 20) & 0xffu);
+        const unsigned ib = ((d.z & 0x000fffffu) << 4) | ((d.w >> 24) & 0xfu);
+        const double v2 = __longlong_as_double((long long)(((unsigned long long)vhi << 32) | vlo));
+        const int i2 = (ib == 0xffffffu) ? INT_MAX : base + (int)ib;
+        const bool wn = beats(v2, i2, gv, gi);
+        gv = wn ? v2 : gv;
+        gi = wn ? i2 : gi;
+        gph = wn ? (int)(d.w & 0x00ffffffu) : gph;
+    };
+    // thread 0: reduce the per-wave candidates in red_* (waves without a
+    // candidate hold v = 0, idx = INT_MAX)
+    auto reduce_red = [&](double &bv, int &bi, int &bph) {
+        double rv[NW];
+        int ri[NW], rph[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            rv[q] = red_v[q];
+            ri[q] = red_i[q];
+            rph[q] = red_ph[q];
+        }
+        bv = rv[0];
+        bi = ri[0];
+        bph = rph[0];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) {
+            const bool wn = beats(rv[q], ri[q], bv, bi);
+            bv = wn ? rv[q] : bv;
+            bi = wn ? ri[q] : bi;
+            bph = wn ? rph[q] : bph;
+        }
+    };
 
     for (int j = 0; j < nb; ++j) {
         const int c = k0 + j;
@@ -237,31 +324,40 @@ __global__ __launch_bounds__(NT) void panel_kernel(
         //    flushed ring groups from Lreg, the current group from the ring.
         const int gr = (j / TPR) / kRing; // ring group of column j (uniform)
         const bool cand = exists && (pos >= r);
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        // h is read in blocks of kHB slots, all reads of a block issued
+        // before its products (slots of the unflushed group in Lreg are 0).
+        constexpr int kHB = 16;
+        double sacc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < kNS; q += 4) {
-            if (q < gr * kRing) { // uniform
-                s0 += Lreg[q] * hv[sub + TPR * q];
-                if (q + 1 < kNS)
-                    s1 += Lreg[q + 1] * hv[sub + TPR * (q + 1)];
-                if (q + 2 < kNS)
-                    s2 += Lreg[q + 2] * hv[sub + TPR * (q + 2)];
-                if (q + 3 < kNS)
-                    s3 += Lreg[q + 3] * hv[sub + TPR * (q + 3)];
+        for (int qb = 0; qb < kNS; qb += kHB) {
+            if (qb < gr * kRing) { // uniform
+                double hh[kHB];
+#pragma unroll
+                for (int i = 0; i < kHB; ++i)
+                    hh[i] = (qb + i < kNS) ? hv[sub + TPR * (qb + i)] : 0.0;
+#pragma unroll
+                for (int i = 0; i < kHB; ++i)
+                    if (qb + i < kNS)
+                        sacc[i & 3] += Lreg[qb + i] * hh[i];
             }
         }
+        {
+            double hh[kRing];
 #pragma unroll
-        for (int i = 0; i < kRing; i += 2) {
-            s0 += Lnew[i] * hv[sub + TPR * (gr * kRing + i)];
-            s1 += Lnew[i + 1] * hv[sub + TPR * (gr * kRing + i + 1)];
+            for (int i = 0; i < kRing; ++i)
+                hh[i] = hv[sub + TPR * (gr * kRing + i)];
+#pragma unroll
+            for (int i = 0; i < kRing; ++i)
+                sacc[i & 3] += Lnew[i] * hh[i];
         }
-        double s = (s0 + s1) + (s2 + s3);
+        double s = (sacc[0] + sacc[1]) + (sacc[2] + sacc[3]);
 #pragma unroll
         for (int off = TPR >> 1; off >= 1; off >>= 1)
             s += __shfl_xor(s, off, 64);
         const double xv = ycol - s;
 
-        // 3. group argmax: largest |x|, smallest row index on ties.
+        // 3. group argmax: largest |x|, smallest row index on ties (each
+        //    wave, then thread 0 over the waves).
         double cv = 0.0;
         int ci = INT_MAX, cph = 0;
         if (cand && sub == 0) {
@@ -269,73 +365,45 @@ __global__ __launch_bounds__(NT) void panel_kernel(
             ci = pos;
             cph = phys;
         }
-#pragma unroll
-        for (int off = 32; off >= TPR; off >>= 1) {
-            const double ov = __shfl_xor(cv, off, 64);
-            const int oi = __shfl_xor(ci, off, 64);
-            const int oph = __shfl_xor(cph, off, 64);
-            if (beats(ov, oi, cv, ci)) {
-                cv = ov;
-                ci = oi;
-                cph = oph;
-            }
-        }
+        wave_argmax(cv, ci, cph);
         if (lane == 0) {
             red_v[wave] = cv;
             red_i[wave] = ci;
             red_ph[wave] = cph;
         }
         // this wave's mirror stores of the previous step must be complete
-        // before this step's slot is published
+        // before the group's slot is published
         if (multi)
             wait_vm();
         __syncthreads();
-
         if (tid == 0) {
-            double bv = red_v[0];
-            int bi = red_i[0], bph = red_ph[0];
-#pragma unroll
-            for (int q = 1; q < NW; ++q) {
-                if (beats(red_v[q], red_i[q], bv, bi)) {
-                    bv = red_v[q];
-                    bi = red_i[q];
-                    bph = red_ph[q];
-                }
-            }
             if (multi) {
-                unsigned long long *wv =
-                    sl64 + (size_t)(par * kMaxPanelGroups + w) * (sizeof(Slot) / 8);
-                const unsigned long long xb = (unsigned long long)__double_as_longlong(bv);
-                const unsigned s16 = stamp & 0xffffu;
-                st_xcd(&wv[0], sw(stamp, (unsigned)(xb >> 32)), local);
-                st_xcd(&wv[1], sw(stamp, (unsigned)(xb & 0xffffffffu)), local);
-                // row relative to the panel base (0xffffff: none) and mirror
-                // row, 24 bits each, under a 16-bit stamp
-                const unsigned ib = (bi == INT_MAX) ? 0xffffffu : (unsigned)(bi - base);
-                st_xcd(&wv[2], ((unsigned long long)s16 << 48) |
-                                   ((unsigned long long)ib << 24) | (unsigned)bph, local);
+                double bv;
+                int bi, bph;
+                reduce_red(bv, bi, bph);
+                publish_slot(par * kSlotsPerParity + w, stamp, bv, bi, bph);
             } else {
+                double bv;
+                int bi, bph;
+                reduce_red(bv, bi, bph);
                 set_pivot(bv, bi, bph);
             }
         }
 
-        // 4. several groups: poll all slots (one per thread) and reduce them
-        //    identically in every group.
+        // 4. several groups: poll all slots and reduce them identically in
+        //    every group.
         if (multi) {
             double gv = 0.0;
             int gi = INT_MAX, gph = 0;
-            const unsigned s16 = stamp & 0xffffu;
             for (int q = tid; q < G; q += NT) {
-                const unsigned long long *wv =
-                    sl64 + (size_t)(par * kMaxPanelGroups + q) * (sizeof(Slot) / 8);
-                unsigned long long w0, w1, w2;
+                u32x4 d;
                 long spins = 0;
                 for (;;) {
-                    w0 = ld_dev(&wv[0]);
-                    w1 = ld_dev(&wv[1]);
-                    w2 = ld_dev(&wv[2]);
-                    if ((unsigned)(w0 >> 32) == stamp && (unsigned)(w1 >> 32) == stamp &&
-                        (unsigned)(w2 >> 48) == s16)
+                    // compiler-only fence: the slot load is an ordinary
+                    // intrinsic and would otherwise be hoisted out of the spin
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    d = load_slot(par * kSlotsPerParity + q);
+                    if (slot_ready(d, stamp))
                         break;
                     if (bc_fail || ++spins > kSpinLimit) {
                         bc_fail = 1;
@@ -343,65 +411,29 @@ __global__ __launch_bounds__(NT) void panel_kernel(
                     }
                     __builtin_amdgcn_s_sleep(1);
                 }
-                const double v2 = __longlong_as_double(
-                    (long long)(((w0 & 0xffffffffull) << 32) | (w1 & 0xffffffffull)));
-                const unsigned ib = (unsigned)((w2 >> 24) & 0xffffffu);
-                const int i2 = (ib == 0xffffffu) ? INT_MAX : base + (int)ib;
-                if (beats(v2, i2, gv, gi)) {
-                    gv = v2;
-                    gi = i2;
-                    gph = (int)(w2 & 0xffffffu);
-                }
+                fold_slot(d, gv, gi, gph);
             }
             if (G <= 64) {
                 // every candidate is in wave 0: reduce there, no barrier
                 if (wave == 0) {
-#pragma unroll
-                    for (int off = 32; off >= 1; off >>= 1) {
-                        const double ov = __shfl_xor(gv, off, 64);
-                        const int oi = __shfl_xor(gi, off, 64);
-                        const int oph = __shfl_xor(gph, off, 64);
-                        if (beats(ov, oi, gv, gi)) {
-                            gv = ov;
-                            gi = oi;
-                            gph = oph;
-                        }
-                    }
+                    wave_argmax(gv, gi, gph);
                     if (lane == 0)
                         set_pivot(gv, gi, gph);
                 }
             } else {
-                // reduce the candidates held by the waves that polled
-                if (wave * 64 < G) {
-#pragma unroll
-                    for (int off = 32; off >= 1; off >>= 1) {
-                        const double ov = __shfl_xor(gv, off, 64);
-                        const int oi = __shfl_xor(gi, off, 64);
-                        const int oph = __shfl_xor(gph, off, 64);
-                        if (beats(ov, oi, gv, gi)) {
-                            gv = ov;
-                            gi = oi;
-                            gph = oph;
-                        }
-                    }
-                }
+                if (wave * 64 < G)
+                    wave_argmax(gv, gi, gph);
                 __syncthreads(); // red_* of step 3 were consumed by thread 0
-                if (lane == 0 && wave * 64 < G) {
+                if (lane == 0) {
                     red_v[wave] = gv;
                     red_i[wave] = gi;
                     red_ph[wave] = gph;
                 }
                 __syncthreads();
                 if (tid == 0) {
-                    double bv = red_v[0];
-                    int bi = red_i[0], bph = red_ph[0];
-                    for (int q = 1; q * 64 < G; ++q) {
-                        if (beats(red_v[q], red_i[q], bv, bi)) {
-                            bv = red_v[q];
-                            bi = red_i[q];
-                            bph = red_ph[q];
-                        }
-                    }
+                    double bv;
+                    int bi, bph;
+                    reduce_red(bv, bi, bph);
                     set_pivot(bv, bi, bph);
                 }
             }
