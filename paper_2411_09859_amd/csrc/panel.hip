@@ -147,6 +147,9 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     __shared__ int red_i[NW], red_ph[NW];
     __shared__ double bc_tau;
     __shared__ int bc_p, bc_physp, bc_fail;
+    __shared__ double hand_v; // wave 1 -> wave 0 handoff of polled candidates
+    __shared__ int hand_i, hand_ph;
+    __shared__ unsigned hand_flag;
 
 
     const int tid = threadIdx.x;
@@ -211,8 +214,10 @@ __global__ __launch_bounds__(NT) void panel_kernel(
         ycol = W[(size_t)k0 * ldw + orow];
     }
     ycol = __shfl(ycol, lane & ~(TPR - 1), 64);
-    if (tid == 0)
+    if (tid == 0) {
         bc_fail = 0;
+        hand_flag = 0u;
+    }
     __syncthreads();
 
     // Broadcast the step's pivot through LDS; an index that does not name an
@@ -413,12 +418,41 @@ __global__ __launch_bounds__(NT) void panel_kernel(
                 }
                 fold_slot(d, gv, gi, gph);
             }
-            if (G <= 64) {
-                // every candidate is in wave 0: reduce there, no barrier
-                if (wave == 0) {
+            if (G <= 128) {
+                // every candidate is in waves 0 and 1: wave 1 hands its
+                // result to wave 0 through LDS (no barrier), wave 0
+                // broadcasts the pivot
+                if (wave == 1 && G > 64) {
                     wave_argmax(gv, gi, gph);
-                    if (lane == 0)
+                    if (lane == 0) {
+                        hand_v = gv;
+                        hand_i = gi;
+                        hand_ph = gph;
+                        __hip_atomic_store(&hand_flag, stamp, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                } else if (wave == 0) {
+                    wave_argmax(gv, gi, gph);
+                    if (lane == 0) {
+                        if (G > 64) {
+                            long hs = 0;
+                            while (__hip_atomic_load(&hand_flag, __ATOMIC_ACQUIRE,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP) != stamp) {
+                                if (++hs > kSpinLimit) {
+                                    bc_fail = 1;
+                                    break;
+                                }
+                                __builtin_amdgcn_s_sleep(1);
+                            }
+                            const double hv2 = hand_v;
+                            const int hi2 = hand_i, hph2 = hand_ph;
+                            const bool wn = beats(hv2, hi2, gv, gi);
+                            gv = wn ? hv2 : gv;
+                            gi = wn ? hi2 : gi;
+                            gph = wn ? hph2 : gph;
+                        }
                         set_pivot(gv, gi, gph);
+                    }
                 }
             } else {
                 if (wave * 64 < G)

@@ -26,8 +26,9 @@
 // transposed tile, D[j][i], so that each lane's four accumulator values lie
 // in four columns at one row i and sixteen consecutive lanes cover sixteen
 // consecutive rows: loads of C and stores of the lower entries are 128-byte
-// segments (the mirrored upper stores are 32-byte pieces of lines that the
-// L2 completes before writing them back).  Tiles are
+// segments, and the mirrored upper entries go out through an LDS transpose
+// as 512-byte column pieces; all C stores are streaming (non-temporal): the
+// next reader is the next panel or update, long after.  Tiles are
 // enumerated over the lower triangle only; a diagonal tile skips the wave
 // whose 64x64 quarter lies strictly above the diagonal and masks the rest.
 // Consecutive tile indices go to one XCD (workgroup ids are dealt to the 8
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict_
                 double v = 0.0;
                 if (gi < n && gj < gi) {
                     v = kF64 ? (double)acc[bi][bj][q] : *csrc(gi, gj) + (double)acc[bi][bj][q];
-                    Wn[(size_t)gj * ldw + gi] = v;
+                    __builtin_nontemporal_store(v, &Wn[(size_t)gj * ldw + gi]);
                 }
                 tr[lrow * TRS + jl] = v;
             }
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict_
             const int gi2 = ib + bi * 16 + rr;
             const double v = tr[rr * TRS + lane];
             if (gi2 < n && gj < gi2)
-                Wn[(size_t)gi2 * ldw + gj] = -v;
+                __builtin_nontemporal_store(-v, &Wn[(size_t)gi2 * ldw + gj]);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();

@@ -65,14 +65,15 @@ def probe_residual(torch, A0dev, Af, t, ipiv, nprobe=3):
     return worst
 
 
-def test_n16384_graded_prefix_parity_and_residual():
+@pytest.mark.parametrize("b", [0, 128])
+def test_n16384_graded_prefix_parity_and_residual(b):
     import torch
     n, steps = 16384, 48
-    note(f"[large] n={n} graded: factor + oracle prefix of {steps} steps")
+    note(f"[large] n={n} b={b} graded: factor + oracle prefix of {steps} steps")
     A = inputs.skew_graded(n, 3, full=False)
     A0 = binding.to_device_colmajor(A)
     Af = A0.clone()
-    t, ipiv, la, sg = device_factor(Af)
+    t, ipiv, la, sg = device_factor(Af, b=b)
     ref = oracle.ltlt(A, max_steps=steps)
     gp = ipiv.cpu().numpy()
     assert gp[0] == 0 and np.array_equal(gp[: steps + 1], ref["ipiv"][: steps + 1])
