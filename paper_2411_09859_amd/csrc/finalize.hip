@@ -9,7 +9,8 @@
 // columns again, so here every column of L receives all of its later
 // exchanges at once at the end: column j gets the composition of the
 // transpositions of all steps after the panel that last wrote it, applied as
-// one gather through LDS (read the column once, write it once, coalesced).
+// one gather per column held in registers (read the column once, write it
+// once, coalesced).
 //
 // Pfaffian: Pf(A) = det(P) * prod_i T[2i][2i+1] (definition in Sec. 1 with
 // Pf(B X B^T) = det(B) Pf(X), T of Sec. 1 / eq. (TvsS): T[2i][2i+1] = -t[2i]).
@@ -66,54 +67,109 @@ __global__ void suffix_map_kernel(const int *__restrict__ ipiv, int n, int b, in
     int v = i;
     gmap[(size_t)(nblk - 1) * n + i] = v;
     for (int B = nblk - 2; B >= 0; --B) {
-        const int s_lo = (B + 1) * b;                       // first step of block B+1
-        const int s_hi = min((B + 2) * b, n - 1);           // end of block B+1
-        for (int c = s_hi - 1; c >= s_lo; --c) {
+        const int s_lo = (B + 1) * b;             // first step of block B+1
+        const int s_hi = min((B + 2) * b, n - 1); // end of block B+1
+        int c = s_hi - 1;
+        // pivots are read 16 at a time (uniform addresses, independent of
+        // v), then applied in order
+        for (; c - 15 >= s_lo; c -= 16) {
+            int pp[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                pp[k] = ipiv[c - k + 1];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int rr = c - k + 1;
+                v = (v == rr) ? pp[k] : ((v == pp[k]) ? rr : v);
+            }
+        }
+        for (; c >= s_lo; --c) {
             const int rr = c + 1;
             const int pp = ipiv[rr];
-            if (v == rr)
-                v = pp;
-            else if (v == pp)
-                v = rr;
+            v = (v == rr) ? pp : ((v == pp) ? rr : v);
         }
         gmap[(size_t)B * n + i] = v;
     }
 }
 
-// One workgroup per stored column a = j-1 of L column j.
-__global__ __launch_bounds__(256) void gather_kernel(double *__restrict__ A, int lda, int n,
-                                                     int b, int nblk,
-                                                     const int *__restrict__ gmap)
+// Column a (holding L column j = a + 1) of block B = j / b receives the
+// exchanges of the steps after block B: rows >= lo take row gmap[B][row].
+struct GatherCol {
+    int B, lo, len;
+};
+__device__ __forceinline__ GatherCol gather_col(int a, int n, int b, int nblk)
 {
-    extern __shared__ double col[];
-    const int a = blockIdx.x; // A column, holds L column j = a + 1
+    GatherCol g;
     const int j = a + 1;
-    const int B = j / b;
-    if (B >= nblk - 1)
-        return; // the last block has no later exchanges
-    const int s = min((B + 1) * b, n - 1);
-    const int lo = s + 1; // rows >= lo can move
-    const int len = n - lo;
-    if (len <= 0)
+    g.B = j / b;
+    const int s = min((g.B + 1) * b, n - 1);
+    g.lo = s + 1;
+    g.len = (g.B >= nblk - 1) ? 0 : n - g.lo; // the last block has no later exchanges
+    return g;
+}
+
+// One 1024-thread workgroup per column, the column held in registers (E per
+// thread): every source is read before the barrier and every destination
+// written after it, so the in-place permutation needs no staging buffer.
+template <int E>
+__global__ __launch_bounds__(1024) void gather_reg_kernel(double *__restrict__ A, int lda, int n,
+                                                          int b, int nblk,
+                                                          const int *__restrict__ gmap)
+{
+    const int a = blockIdx.x;
+    const GatherCol gc = gather_col(a, n, b, nblk);
+    if (gc.len <= 0)
         return;
-    double *cp = A + (size_t)a * lda + lo;
-    for (int q = threadIdx.x; q < len; q += blockDim.x)
-        col[q] = cp[q];
+    double *cp = A + (size_t)a * lda + gc.lo;
+    const int *g = gmap + (size_t)gc.B * n + gc.lo;
+    double v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int q = threadIdx.x + e * 1024;
+        v[e] = 0.0;
+        if (q < gc.len) {
+            int src = g[q] - gc.lo;
+            if (src < 0 || src >= gc.len)
+                src = q; // cannot happen for valid pivots; keeps the read in range
+            v[e] = cp[src];
+        }
+    }
     __syncthreads();
-    const int *g = gmap + (size_t)B * n + lo;
-    for (int q = threadIdx.x; q < len; q += blockDim.x) {
-        int src = g[q] - lo;
-        if (src < 0 || src >= len)
-            src = q; // cannot happen for valid pivots; keeps the LDS read in range
-        cp[q] = col[src];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int q = threadIdx.x + e * 1024;
+        if (q < gc.len)
+            cp[q] = v[e];
     }
 }
 
-void finalize_init_attrs()
+// Columns longer than the register version holds: gather into a scratch
+// column of the (no longer needed) work matrix, then copy back.
+__global__ __launch_bounds__(1024) void gather_scratch_kernel(double *__restrict__ A, int lda,
+                                                              int n, int b, int nblk,
+                                                              const int *__restrict__ gmap,
+                                                              double *__restrict__ scratch,
+                                                              int lds_)
 {
-    (void)hipFuncSetAttribute((const void *)gather_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        160 * 1024);
+    const int a = blockIdx.x;
+    const GatherCol gc = gather_col(a, n, b, nblk);
+    if (gc.len <= 0)
+        return;
+    double *cp = A + (size_t)a * lda + gc.lo;
+    double *tmp = scratch + (size_t)a * lds_;
+    const int *g = gmap + (size_t)gc.B * n + gc.lo;
+    for (int q = threadIdx.x; q < gc.len; q += blockDim.x) {
+        int src = g[q] - gc.lo;
+        if (src < 0 || src >= gc.len)
+            src = q;
+        tmp[q] = cp[src];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < gc.len; q += blockDim.x)
+        cp[q] = tmp[q];
 }
+
+void finalize_init_attrs() {}
 
 hipError_t launch_finalize(double *A, int lda, int n, int b, const int *ipiv,
                            const FactorWs &ws, hipStream_t s)
@@ -133,9 +189,19 @@ hipError_t launch_finalize(double *A, int lda, int n, int b, const int *ipiv,
     const int maxlen = n - (b + 1);
     if (maxlen <= 0)
         return hipSuccess;
-    const size_t lds = sizeof(double) * (size_t)maxlen;
-    hipLaunchKernelGGL(gather_kernel, dim3(n - 2 > 0 ? n - 2 : 1), dim3(256), lds, s, A, lda, n,
-                       b, nblk, (const int *)ws.gmap);
+    const dim3 grid(n - 2 > 0 ? n - 2 : 1), blk(1024);
+    const int *gm = ws.gmap;
+    if (maxlen <= 4 * 1024)
+        hipLaunchKernelGGL(gather_reg_kernel<4>, grid, blk, 0, s, A, lda, n, b, nblk, gm);
+    else if (maxlen <= 8 * 1024)
+        hipLaunchKernelGGL(gather_reg_kernel<8>, grid, blk, 0, s, A, lda, n, b, nblk, gm);
+    else if (maxlen <= 16 * 1024)
+        hipLaunchKernelGGL(gather_reg_kernel<16>, grid, blk, 0, s, A, lda, n, b, nblk, gm);
+    else if (maxlen <= 32 * 1024)
+        hipLaunchKernelGGL(gather_reg_kernel<32>, grid, blk, 0, s, A, lda, n, b, nblk, gm);
+    else
+        hipLaunchKernelGGL(gather_scratch_kernel, grid, blk, 0, s, A, lda, n, b, nblk, gm,
+                           ws.W[0], ws.ldw);
     return hipGetLastError();
 }
 

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void init_full_kernel(const double *__restrict
                 v = -tile[r][c]; // diagonal tile: upper entry from the lower one
             else
                 v = 0.0;
-            W[(size_t)gj * ldw + gi] = v;
+            __builtin_nontemporal_store(v, &W[(size_t)gj * ldw + gi]);
         }
     }
     if (I == J)
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void init_full_kernel(const double *__restrict
     for (int c = tid / TT; c < TT; c += 256 / TT) {
         const int wi = j0 + r, wj = i0 + c;
         if (wi < n && wj < n)
-            W[(size_t)wj * ldw + wi] = -tile[r][c];
+            __builtin_nontemporal_store(-tile[r][c], &W[(size_t)wj * ldw + wi]);
     }
 }
 

@@ -123,16 +123,13 @@ static int resolve_block(int n, int block_size)
     return block_size > 0 ? block_size : skltlt_default_block_size(n);
 }
 
-// Supported: panel LDS (rows per group x (b+2) doubles) and the gather
-// column (n - b - 1 doubles) fit in one CU's LDS.
+// Supported: panel widths up to kMaxBlock, and orders whose panel fits the
+// slot array (256 rows per group at most 1024 groups).  Whether the panel's
+// groups can all be resident is checked when the factorization runs.
 static int check_supported(int n, int b)
 {
     if (b < 1 || b > kMaxBlock)
         return SKLTLT_ENOTSUP;
-    const size_t gather = sizeof(double) * (size_t)(n > b + 1 ? n - b - 1 : 0);
-    if (gather > kLdsCap)
-        return SKLTLT_ENOTSUP;
-    // rows per group at most 256 with 1024 groups
     if (n > 256 * kMaxPanelGroups)
         return SKLTLT_ENOTSUP;
     return SKLTLT_OK;
