@@ -15,13 +15,11 @@ constexpr int kMaxBlock = 256;       // largest supported panel width
 constexpr int kSlotsPerParity = kMaxPanelGroups;
 constexpr size_t kAlign = 256;
 
-// One record per panel workgroup and step parity, a cache line of its own: eight
-// 8-byte words, of which the panel uses three, each carrying the step stamp:
-// [0] and [1] the high and low halves of the candidate value under a 32-bit
-// stamp, [2] a 16-bit stamp, the candidate row relative to the panel base
-// and its register row (24 bits each).
-struct alignas(64) Slot {
-    unsigned long long w[8];
+// Pivot exchange slots: one 16-byte record per panel workgroup and step
+// parity (layout in the panel kernel), one L2 line apart.
+constexpr int kSlotBytes = 128;
+struct Slot {
+    unsigned int w[4];
 };
 
 // Device workspace of skltlt_factor, carved from the caller's buffer.

@@ -242,8 +242,10 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     // (24 bits, 0xffffff: none) and its register row (24 bits).  A reader
     // accepts the slot when all four stamps match, so a read that mixes two
     // writes is never taken for a complete one.
+    // Each slot has a 128-byte L2 line of its own: slots that share a line
+    // make writers on different XCDs contend for it (measured slower).
     const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)slots, (short)0, (int)(sizeof(Slot) * 2 * kSlotsPerParity), 0x00020000);
+        (void *)slots, (short)0, (int)(kSlotBytes * 2 * kSlotsPerParity), 0x00020000);
     auto publish_slot = [&](int q, unsigned stamp, double v, int idx, int ph) {
         const unsigned long long xb = (unsigned long long)__double_as_longlong(v);
         const unsigned vhi = (unsigned)(xb >> 32), vlo = (unsigned)xb;
@@ -255,12 +257,12 @@ __global__ __launch_bounds__(NT) void panel_kernel(
         d.z = st | ((vlo & 0xffu) << 20) | (ib >> 4);
         d.w = st | ((ib & 0xfu) << 24) | ((unsigned)ph & 0xffffffu);
         if (local)
-            __builtin_amdgcn_raw_buffer_store_b128(d, srs, q * (int)sizeof(Slot), 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(d, srs, q * kSlotBytes, 0, 0);
         else // device scope (sc1): visible to other XCDs without an L2 write-back
-            __builtin_amdgcn_raw_buffer_store_b128(d, srs, q * (int)sizeof(Slot), 0, 16);
+            __builtin_amdgcn_raw_buffer_store_b128(d, srs, q * kSlotBytes, 0, 16);
     };
     auto load_slot = [&](int q) {
-        return __builtin_amdgcn_raw_buffer_load_b128(srs, q * (int)sizeof(Slot), 0, 16);
+        return __builtin_amdgcn_raw_buffer_load_b128(srs, q * kSlotBytes, 0, 16);
     };
     auto slot_ready = [](u32x4 d, unsigned stamp) {
         const unsigned s4 = stamp & 0xfu;
