@@ -126,35 +126,35 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict_
     constexpr int PER = (KC * TM) / 256; // elements per thread per operand and chunk
     T ri[PER], rj[PER];
 
+    // Every load below is issued unconditionally (clamped address) and
+    // masked only when the chunk is written to LDS: with a fixed number of
+    // loads per chunk and no use right after them, the compiler waits for
+    // the chunk that is due while the prefetched one stays in flight (loads
+    // skipped by branches, or used at once, make it wait for all of them).
     auto load_chunk = [&](int kc) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = tid + q * 256;
             const int rr = e % TM;
             const int k = kc * KC + e / TM;
-            const int gi = i0 + rr, gj = j0 + rr;
-            T vi = 0, vj = 0;
-            if (k < K) {
-                if (gi < n)
-                    vi = opI[(size_t)k * n + gi];
-                if (gj < n)
-                    vj = opJ[(size_t)k * n + gj];
-            }
-            ri[q] = vi;
-            rj[q] = vj;
+            const int kk = (k < K) ? k : 0;
+            ri[q] = opI[(size_t)kk * n + min(i0 + rr, n - 1)];
+            rj[q] = opJ[(size_t)kk * n + min(j0 + rr, n - 1)];
         }
     };
-    auto store_chunk = [&](int buf) {
+    auto store_chunk = [&](int buf, int kc) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = tid + q * 256;
-            sI[buf][e / TM][e % TM] = ri[q];
-            sJ[buf][e / TM][e % TM] = rj[q];
+            const int rr = e % TM;
+            const bool kok = kc * KC + e / TM < K;
+            sI[buf][e / TM][rr] = (kok && i0 + rr < n) ? ri[q] : (T)0;
+            sJ[buf][e / TM][rr] = (kok && j0 + rr < n) ? rj[q] : (T)0;
         }
     };
 
     load_chunk(0);
-    store_chunk(0);
+    store_chunk(0, 0);
     if (nk > 1)
         load_chunk(1);
     __syncthreads();
@@ -171,8 +171,11 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict_
             for (int q = 0; q < 4; ++q) {
                 const int gj = jb + bj * 16 + MfmaT<T>::drow(lk, q);
                 T v = 0;
-                if (kF64 && active && gi < n && gj < gi)
-                    v = (T)*csrc(gi, gj);
+                if (kF64) {
+                    // rows/columns past n have source row 0: still in range
+                    const double cv = *csrc(gi, gj);
+                    v = (active && gi < n && gj < gi) ? (T)cv : (T)0;
+                }
                 acc[bi][bj][q] = v;
             }
         }
@@ -180,7 +183,7 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict_
     for (int kc = 0; kc < nk; ++kc) {
         const int cur = kc & 1;
         if (kc + 1 < nk) {
-            store_chunk(cur ^ 1); // buffer freed by the barrier ending step kc-1
+            store_chunk(cur ^ 1, kc + 1); // buffer freed by the barrier ending step kc-1
             if (kc + 2 < nk)
                 load_chunk(kc + 2); // in flight during this chunk's MFMAs
         }
