@@ -55,8 +55,9 @@ def kernel_times(lib):
 
 def skr2k_bytes(n, b):
     """Algorithmic HBM bytes of all skr2k launches of one factorization: each
-    launch reads and writes the strict lower triangle of the trailing block
-    once (16 B per element) and reads the two m x K operand panels once."""
+    launch reads the strict lower triangle of the trailing block once (8 B
+    per element, at permuted positions), writes it and its negated mirror
+    (16 B per element) and reads the two m x K operand panels once."""
     tot = 0.0
     k0 = 0
     while k0 < n - 1:
@@ -65,9 +66,37 @@ def skr2k_bytes(n, b):
         m = n - cp
         if cp < n - 1 and m >= 2:
             K = 2 * ((nb + 1) // 2)
-            tot += 16.0 * m * (m - 1) / 2.0 + 8.0 * m * 2 * K
+            tot += 24.0 * m * (m - 1) / 2.0 + 16.0 * m * K
         k0 = cp
     return tot
+
+
+def panel_flops(n, b):
+    """FP64 flops of the panel's left-looking products x = y - L h (2 flops
+    per stored L entry of every candidate row at every column step)."""
+    tot = 0.0
+    for c in range(n - 1):
+        j = c % b
+        tot += 2.0 * (n - c - 1) * (j + 1)
+    return tot
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "skr2k_n16384_b256_traffic.txt")
+
+
+def measured_traffic(n, b):
+    """Counter-measured HBM bytes per skr2k launch from the committed summary,
+    or None with the reason when it does not describe this kernel/workload."""
+    from paper_2411_09859_amd import profsum
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None, "no counter summary"
+    v = profsum.read_summary(TRAFFIC_SUMMARY)
+    if v.get("workload") != f"n={n} b={b}":
+        return None, "counters were taken at another workload"
+    src = os.path.join(ROOT, v.get("source", ""))
+    if not os.path.exists(src) or profsum.sha256_of(src) != v.get("source_sha256"):
+        return None, "kernel source changed since the counters were taken"
+    return float(v["traffic_bytes_per_launch"]), os.path.relpath(TRAFFIC_SUMMARY, ROOT)
 
 
 def resid_probe(torch, A0, Af, t, ipiv, nprobe=4, seed=0):
@@ -304,7 +333,8 @@ def main():
             fp32["resid_probe"] = resid_probe(torch, A0, Aw, t, ipiv)
         log(f"[bench] FP32-update {fp32}")
 
-    # roofline of the dominant kernel class
+    # roofline of the throughput-bound kernel (the trailing update); the
+    # panel is latency-bound and reported by its per-step time
     dom = max(("skr2k", "panel"), key=lambda k: kt.get(k, {}).get("total_ms", 0.0))
     roof = None
     if "skr2k" in kt:
@@ -314,13 +344,25 @@ def main():
         flops_per_launch = sk["flops"] / sk["launches"]
         achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
         bytes_per_launch = skr2k_bytes(n, b) * steps / sk["launches"]
+        traffic, traffic_src = measured_traffic(n, b)
         roof = {"kernel": "skr2k_kernel<double>", "bound": "mfma", "achieved": achieved,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": None, "flops_per_launch": flops_per_launch,
+                "traffic": traffic, "traffic_source": traffic_src,
+                "flops_per_launch": flops_per_launch,
                 "algorithmic_bytes_per_launch": bytes_per_launch,
                 "avg_launch_ms": per_launch_ms,
                 "hbm_gbs_algorithmic": bytes_per_launch / (per_launch_ms * 1e-3) / 1e9,
+                "hbm_frac_algorithmic": bytes_per_launch / (per_launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
                 "dominant_class_by_time": dom}
+    panel = None
+    if "panel" in kt:
+        pk = kt["panel"]
+        pms = pk["total_ms"] / args.steps
+        pf = panel_flops(n, b)
+        panel = {"bound": "latency", "ms_per_step": pms,
+                 "us_per_column_step": pms * 1e3 / (n - 1),
+                 "alu_flops": pf, "alu_tflops": pf / (pms * 1e-3) / 1e12,
+                 "alu_frac": pf / (pms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
 
     # CPU oracle on a bounded sample
     cpu = None
@@ -368,6 +410,7 @@ def main():
                                f"N(0,1)*10^U(-6,6), seed {args.seed}, FP64",
                    "n": n, "block_size": b},
         "roofline": roof,
+        "panel": panel,
         "cpu_baseline": cpu,
         "kernels": kt,
         "fp32_update": fp32,

@@ -127,6 +127,7 @@ def cmd_traffic(args):
              f"# fetch run:  {args.cmd_fetch}",
              f"# write run:  {args.cmd_write}",
              f"# calibration: {args.cmd_calib} (FETCH_SIZE and WRITE_SIZE runs)",
+             f"workload: {args.workload}",
              f"kernel_regex: {args.kernel}",
              f"source: {args.source}",
              f"source_sha256: {sha256_of(args.source)}",
@@ -172,6 +173,7 @@ def main(argv=None):
     a.add_argument("--cmd-write", required=True)
     a.add_argument("--cmd-calib", required=True)
     a.add_argument("--title", default="HBM traffic per launch")
+    a.add_argument("--workload", required=True, help='e.g. "n=16384 b=256"')
     a.add_argument("--out", required=True)
     args = ap.parse_args(argv)
     {"copy": cmd_copy, "stats": cmd_stats, "traffic": cmd_traffic}[args.cmd](args)
