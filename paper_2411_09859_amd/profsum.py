@@ -151,7 +151,7 @@ def cmd_traffic(args):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    sub = ap.add_subparsers(dest="cmd", required=True)
+    sub = ap.add_subparsers(dest="sub", required=True)
     a = sub.add_parser("copy")
     a.add_argument("--mib", type=int, default=1024)
     a.add_argument("--reps", type=int, default=3)
@@ -176,7 +176,7 @@ def main(argv=None):
     a.add_argument("--workload", required=True, help='e.g. "n=16384 b=256"')
     a.add_argument("--out", required=True)
     args = ap.parse_args(argv)
-    {"copy": cmd_copy, "stats": cmd_stats, "traffic": cmd_traffic}[args.cmd](args)
+    {"copy": cmd_copy, "stats": cmd_stats, "traffic": cmd_traffic}[args.sub](args)
 
 
 if __name__ == "__main__":
