@@ -80,6 +80,36 @@ __device__ __forceinline__ void tile_of(int tau, int *ti, int *tj)
     *tj = tau - I * (I + 1) / 2;
 }
 
+// The same tiles in blocks of S tile rows x S tile columns: block rows in
+// order, inside a block row the full blocks left to right (column-major
+// inside a block) and the triangular diagonal block last, so that tiles
+// processed together share operand panels in L2 (nt: tiles per side).
+template <int S>
+__device__ __forceinline__ void tile_of_blocked(int tau, int nt, int *ti, int *tj)
+{
+    int r, c;
+    tile_of(tau, &r, &c); // block rows are contiguous in both orders
+    const int r0 = (r / S) * S;
+    const int h = min(S, nt - r0);
+    int t = tau - r0 * (r0 + 1) / 2;
+    const int full = r0 * h;
+    if (t < full) {
+        const int BJ = t / (S * h);
+        const int q = t - BJ * S * h;
+        *ti = r0 + q % h;
+        *tj = BJ * S + q / h;
+    } else {
+        t -= full;
+        int a = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while ((a + 1) * (a + 2) / 2 <= t)
+            ++a;
+        while (a * (a + 1) / 2 > t)
+            --a;
+        *ti = r0 + a;
+        *tj = r0 + (t - a * (a + 1) / 2);
+    }
+}
+
 int device_cu_count();
 // Records the HIP error behind an SKLTLT_EDEVICE; returns SKLTLT_EDEVICE.
 int device_error(hipError_t e, const char *where);
