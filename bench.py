@@ -40,7 +40,7 @@ def log(msg):
 
 def kernel_times(lib):
     out = {}
-    names = ["panel", "skr2k", "finalize", "pfaffian", "batched", "other"]
+    names = ["panel", "skr2k", "finalize", "pfaffian", "batched", "other", "solve"]
     for k, nm in enumerate(names):
         ms = ctypes.c_double(0)
         cnt = ctypes.c_int(0)
@@ -236,6 +236,8 @@ def main():
                     help="requests in the serving runs (the full stream has 100000)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--solve-steps", type=int, default=3,
+                    help="timed solves with the factors (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -306,6 +308,36 @@ def main():
     if not args.no_check:
         checks["resid_probe_fp64"] = resid_probe(torch, A0, Aw, t, ipiv)
         log(f"[bench] fp64 residual probe {checks['resid_probe_fp64']:.3e}")
+
+    # solving A x = w with the factors just computed (one right-hand side)
+    solve = None
+    if args.solve_steps > 0:
+        g = torch.Generator(device=dev)
+        g.manual_seed(args.seed)
+        w = torch.randn(n, dtype=torch.float64, device=dev, generator=g)
+        x = torch.empty_like(w)
+        swork = binding.alloc_workspace(binding.solve_workspace_size(n, 1), dev)
+        x.copy_(w)
+        binding.solve(Aw, t, ipiv, x, swork, stream)
+        torch.cuda.synchronize()
+        sms = []
+        for _ in range(args.solve_steps):
+            x.copy_(w)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            binding.solve(Aw, t, ipiv, x, swork, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sms.append(e0.elapsed_time(e1))
+        low = torch.tril(A0, -1)
+        r = (low - low.T) @ x - w
+        nA = torch.linalg.norm(low) * 2 ** 0.5
+        solve = {"n": n, "nrhs": 1, "ms": float(np.median(sms)),
+                 "backward_error": (torch.linalg.norm(r) / (nA * torch.linalg.norm(x))).item()}
+        del low, r
+        log(f"[bench] solve {solve}")
 
     # FP32-update variant
     fp32 = None
@@ -411,6 +443,7 @@ def main():
                    "n": n, "block_size": b},
         "roofline": roof,
         "panel": panel,
+        "solve": solve,
         "cpu_baseline": cpu,
         "kernels": kt,
         "fp32_update": fp32,

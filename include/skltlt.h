@@ -145,6 +145,32 @@ int skltlt_batched(int batch, const int *n, double *const *A, const int *lda,
  * the calling thread ("" if none).  Static storage, never NULL. */
 const char *skltlt_last_device_error(void);
 
+/* ---- Solving with the factors ------------------------------------------
+ * Solve A X = B for a skew-symmetric A factored by skltlt_factor or
+ * skltlt_pfaffian (the factorization serves to solve skew-symmetric systems,
+ * Sec. 1): with P A P^T = L T L^T,
+ *     X = P^T L^{-T} T^{-1} L^{-1} P B,
+ * i.e. permute the rows of B by P, solve with the unit lower L, solve the
+ * skew tridiagonal T (two first-order recurrences: odd unknowns from the
+ * even rows, even unknowns from the odd rows), solve with L^T, undo P.
+ *   n      order; must be even (an odd-order skew matrix is singular)
+ *   nrhs   number of right-hand sides, >= 1
+ *   LT     (device) the factored matrix exactly as the factorization left
+ *          it (L below the subdiagonal, t on it), leading dimension lda >= n
+ *   t      (device) the n-1 entries t of the factorization
+ *   ipiv   (device) its n pivots
+ *   B      (device) n x nrhs, column-major, ldb >= n; overwritten by X
+ *   work   (device) skltlt_solve_workspace_size(n, nrhs) bytes, 256-byte
+ *          aligned
+ * T is singular exactly when some t[2i] = 0 (then Pf(A) = 0): X then holds
+ * non-finite values.  Check the Pfaffian's sign first when that matters.
+ * Returns SKLTLT_EINVAL for n < 0, odd n, nrhs < 1, lda or ldb < n, NULL
+ * pointers or a short or misaligned workspace.  n = 0 does nothing. */
+int skltlt_solve_workspace_size(int n, int nrhs, size_t *bytes);
+int skltlt_solve(int n, int nrhs, const double *LT, int lda, const double *t,
+                 const int *ipiv, double *B, int ldb, void *work, size_t work_bytes,
+                 void *stream);
+
 /* ---- Instrumentation ---------------------------------------------------
  * Per-kernel timing for measurement tools.  While enabled, every kernel the
  * library enqueues is bracketed by a pair of HIP events recorded on the same
@@ -157,7 +183,8 @@ typedef enum {
     SKLTLT_K_PFAFFIAN = 3, /* log|Pf| and sign                               */
     SKLTLT_K_BATCHED = 4,  /* batched persistent kernel                      */
     SKLTLT_K_OTHER = 5,    /* small fills                                    */
-    SKLTLT_K_COUNT = 6
+    SKLTLT_K_SOLVE = 6,    /* skltlt_solve's kernels                         */
+    SKLTLT_K_COUNT = 7
 } skltlt_kernel_class;
 
 /* Start recording; max_launches bounds the number of bracketed launches

@@ -4,10 +4,12 @@ TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke``
 and by the CPU-baseline leg of ``bench.py``.  The GPU library never imports,
 links or calls anything here, and this module never touches the GPU library.
 
-The arithmetic lives in ``skltlt_oracle.c`` (plain C, fp64, full storage); this
-module only compiles it with gcc and marshals numpy arrays through ctypes.
+The factorization's arithmetic lives in ``skltlt_oracle.c`` (plain C, fp64,
+full storage); this module compiles it with gcc and marshals numpy arrays
+through ctypes.  ``solve`` is the definition of a linear solve written out
+with numpy's dense LU (a library primitive as the one step).
 Paper: arXiv 2411.09859, Sec. 2.4 (eq. (1), the Parlett-Reid step), Sec. 3.7
-(pivoting) and Sec. 1 (the Pfaffian).
+(pivoting) and Sec. 1 (the Pfaffian; skew systems as the factorization's use).
 """
 from __future__ import annotations
 
@@ -141,3 +143,12 @@ def perm_from_ipiv(ipiv: np.ndarray) -> np.ndarray:
         if p != r:
             q[r], q[p] = q[p], q[r]
     return q
+
+
+def solve(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """X with A X = B for the skew matrix whose strict lower triangle is ``A``:
+    the definition written out, a dense LU solve of the full matrix (the use
+    of the factorization for skew systems, Sec. 1, is checked against it)."""
+    A = np.asarray(A, dtype=np.float64)
+    low = np.tril(A, -1)
+    return np.linalg.solve(low - low.T, np.asarray(B, dtype=np.float64))

@@ -64,6 +64,10 @@ def lib():
         L.skltlt_batched_workspace_size.restype = i
         L.skltlt_batched.argtypes = [i, vp, vp, vp, vp, vp, vp, vp, vp, i, i, i, vp, sz, vp]
         L.skltlt_batched.restype = i
+        L.skltlt_solve_workspace_size.argtypes = [i, i, ctypes.POINTER(sz)]
+        L.skltlt_solve_workspace_size.restype = i
+        L.skltlt_solve.argtypes = [i, i, vp, i, vp, vp, vp, i, vp, sz, vp]
+        L.skltlt_solve.restype = i
         _lib = L
     return _lib
 
@@ -169,6 +173,37 @@ def batched(n_dev, A_ptrs, lda_dev, t_ptrs, ipiv_ptrs, log_abs_pf, sign, info, m
                               work.numel(), _stream(stream))
     if st != SKLTLT_OK:
         raise SkltltError(st, "skltlt_batched")
+    return st
+
+
+def solve_workspace_size(n: int, nrhs: int = 1) -> int:
+    out = ctypes.c_size_t(0)
+    st = lib().skltlt_solve_workspace_size(int(n), int(nrhs), ctypes.byref(out))
+    if st != SKLTLT_OK:
+        raise SkltltError(st, "skltlt_solve_workspace_size")
+    return int(out.value)
+
+
+def solve(LT, t, ipiv, B, work=None, stream=None):
+    """skltlt_solve on device tensors: LT the factored matrix (column-major
+    view), t (n-1), ipiv (n), B overwritten by X: a 1-D tensor of length n or
+    an n x nrhs column-major view."""
+    n = LT.shape[0]
+    lda = _lda_of(LT)
+    if B.dim() == 1:
+        nrhs, ldb = 1, max(n, 1)
+        if B.shape[0] != n:
+            raise ValueError("B must have n entries")
+    else:
+        if B.shape[0] != n or (n > 1 and B.stride(0) != 1):
+            raise ValueError("B must be an n x nrhs column-major view")
+        nrhs, ldb = B.shape[1], max(B.stride(1), n, 1)
+    if work is None:
+        work = alloc_workspace(solve_workspace_size(n, max(nrhs, 1)), LT.device)
+    st = lib().skltlt_solve(n, int(nrhs), _ptr(LT), lda, _ptr(t), _ptr(ipiv), _ptr(B), ldb,
+                            _ptr(work), work.numel(), _stream(stream))
+    if st != SKLTLT_OK:
+        raise SkltltError(st, "skltlt_solve")
     return st
 
 

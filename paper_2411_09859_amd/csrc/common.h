@@ -40,6 +40,20 @@ struct FactorWs {
 
 size_t factor_ws_layout(int n, int b, FactorWs *ws, char *base);
 
+// Device workspace of skltlt_solve.
+struct SolveWs {
+    int *q;      // row permutation (n)
+    double *Y;   // P B, then L^{-1} P B (n x nrhs, ld)
+    double *U;   // T^{-1} ..., then the solution before the inverse permutation
+    unsigned *flags; // per-block completion words of the single-launch solves (2 x blocks)
+    int ld;
+    size_t bytes;
+};
+size_t solve_ws_layout(int n, int nrhs, SolveWs *ws, char *base);
+hipError_t launch_solve(int n, int nrhs, const double *LT, int lda, const double *t,
+                        const int *ipiv, double *B, int ldb, const SolveWs &ws, hipStream_t s);
+void solve_init_attrs();
+
 // ---- launchers (return hipError_t) -----------------------------------------
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_set_int(int *p, int v, hipStream_t s);

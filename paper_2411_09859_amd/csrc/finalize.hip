@@ -58,37 +58,37 @@ hipError_t launch_set_int(int *p, int v, hipStream_t s)
 // steps after block B are applied to a column (composition of
 // transpositions, last step innermost).  Block B covers steps
 // [B*b, min((B+1)*b, n-1)).
-__global__ void suffix_map_kernel(const int *__restrict__ ipiv, int n, int b, int nblk,
-                                  int *__restrict__ gmap)
+constexpr int kPC = 8192; // pivots staged in LDS per chunk
+__global__ __launch_bounds__(256) void suffix_map_kernel(const int *__restrict__ ipiv, int n,
+                                                         int b, int nblk,
+                                                         int *__restrict__ gmap)
 {
+    // every thread walks all later pivots, so they are staged in LDS a chunk
+    // at a time (their load latency would otherwise serialize the walk)
+    __shared__ int sp[kPC];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
-        return;
     int v = i;
-    gmap[(size_t)(nblk - 1) * n + i] = v;
-    for (int B = nblk - 2; B >= 0; --B) {
-        const int s_lo = (B + 1) * b;             // first step of block B+1
-        const int s_hi = min((B + 2) * b, n - 1); // end of block B+1
-        int c = s_hi - 1;
-        // pivots are read 16 at a time (uniform addresses, independent of
-        // v), then applied in order
-        for (; c - 15 >= s_lo; c -= 16) {
-            int pp[16];
-#pragma unroll
-            for (int k = 0; k < 16; ++k)
-                pp[k] = ipiv[c - k + 1];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int rr = c - k + 1;
-                v = (v == rr) ? pp[k] : ((v == pp[k]) ? rr : v);
+    if (i < n)
+        gmap[(size_t)(nblk - 1) * n + i] = v;
+    // steps c = n-2 down to b (blocks nblk-1 .. 1); pivot of step c is ipiv[c+1]
+    int B = nblk - 2;                  // the map of block B gets the steps of blocks > B
+    int next_store = (B + 1) * b;      // after applying step next_store, store gmap[B]
+    for (int hi = n - 2; hi >= b; hi -= kPC) {
+        const int lo = max(b, hi - kPC + 1);
+        __syncthreads();
+        for (int c = lo + (int)threadIdx.x; c <= hi; c += blockDim.x)
+            sp[c - lo] = ipiv[c + 1];
+        __syncthreads();
+        for (int c = hi; c >= lo; --c) {
+            const int rr = c + 1, pp = sp[c - lo];
+            v = (v == rr) ? pp : ((v == pp) ? rr : v);
+            if (c == next_store) {
+                if (i < n)
+                    gmap[(size_t)B * n + i] = v;
+                --B;
+                next_store -= b;
             }
         }
-        for (; c >= s_lo; --c) {
-            const int rr = c + 1;
-            const int pp = ipiv[rr];
-            v = (v == rr) ? pp : ((v == pp) ? rr : v);
-        }
-        gmap[(size_t)B * n + i] = v;
     }
 }
 

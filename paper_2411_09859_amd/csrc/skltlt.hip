@@ -86,6 +86,7 @@ static void init_device_attrs()
     std::call_once(once, [] {
         panel_init_attrs();
         finalize_init_attrs();
+        solve_init_attrs();
         (void)hipGetLastError();
     });
 }
@@ -250,5 +251,39 @@ extern "C" int skltlt_pfaffian(int n, double *A, int lda, double *t, int *ipiv,
     if (e != hipSuccess)
         return device_error(e, "pfaffian launch");
     tm_end(ti, s, 0.0);
+    return SKLTLT_OK;
+}
+
+extern "C" int skltlt_solve_workspace_size(int n, int nrhs, size_t *bytes)
+{
+    if (n < 0 || nrhs < 1 || !bytes)
+        return SKLTLT_EINVAL;
+    *bytes = solve_ws_layout(n, nrhs, nullptr, nullptr);
+    return SKLTLT_OK;
+}
+
+extern "C" int skltlt_solve(int n, int nrhs, const double *LT, int lda, const double *t,
+                            const int *ipiv, double *B, int ldb, void *work, size_t work_bytes,
+                            void *stream)
+{
+    if (n < 0 || (n & 1) || nrhs < 1)
+        return SKLTLT_EINVAL;
+    if (n == 0)
+        return SKLTLT_OK;
+    if (lda < n || ldb < n || !LT || !t || !ipiv || !B)
+        return SKLTLT_EINVAL;
+    const size_t need = solve_ws_layout(n, nrhs, nullptr, nullptr);
+    if (!work || work_bytes < need || ((uintptr_t)work % kAlign) != 0)
+        return SKLTLT_EINVAL;
+    init_device_attrs();
+    SolveWs ws;
+    solve_ws_layout(n, nrhs, &ws, (char *)work);
+    hipStream_t s = (hipStream_t)stream;
+    const int ti = tm_begin(SKLTLT_K_SOLVE, s);
+    hipError_t e = launch_solve(n, nrhs, LT, lda, t, ipiv, B, ldb, ws, s);
+    if (e != hipSuccess)
+        return device_error(e, "solve launch");
+    // L^{-1}, L^{-T}: n^2 each per right-hand side; T^{-1}: O(n)
+    tm_end(ti, s, 2.0 * (double)n * (double)n * nrhs);
     return SKLTLT_OK;
 }

@@ -257,3 +257,42 @@ def test_pins_pass_on_oracle():
 @pytest.mark.parametrize("mutation", [m for m in oracle.MUTATIONS if m != "none"])
 def test_planted_mistake_is_caught(mutation):
     assert _pin_failures(mutation), f"mutation {mutation} escaped every pin"
+
+
+# ------------------------------------------------------------ solve (oracle)
+def _block_diag_system(n, seed):
+    """A[i, j] = D[q[i], q[j]] with D = diag([[0, a_k], [-a_k, 0]]), and the
+    solution of A v = w in closed form: D v~ = w~ with w~[q[i]] = w[i] gives
+    v~[2k] = -w~[2k+1] / a_k, v~[2k+1] = w~[2k] / a_k, and v[i] = v~[q[i]]."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.5, 2.0, n // 2) * rng.choice([-1.0, 1.0], n // 2)
+    D = np.zeros((n, n))
+    for k in range(n // 2):
+        D[2 * k, 2 * k + 1] = a[k]
+        D[2 * k + 1, 2 * k] = -a[k]
+    q = rng.permutation(n)
+    A = D[np.ix_(q, q)]
+    w = rng.standard_normal((n, 3))
+    wt = np.empty_like(w)
+    wt[q] = w
+    vt = np.empty_like(w)
+    vt[0::2] = -wt[1::2] / a[:, None]
+    vt[1::2] = wt[0::2] / a[:, None]
+    return A, w, vt[q]
+
+
+@pytest.mark.parametrize("n", [2, 6, 40])
+def test_oracle_solve_closed_form(n):
+    A, w, v = _block_diag_system(n, 50 + n)
+    x = oracle.solve(A, w)
+    assert np.allclose(x, v, rtol=1e-13, atol=1e-13)
+
+
+def test_oracle_solve_reads_strict_lower_only():
+    rng = np.random.default_rng(3)
+    A = inputs.skew_normal(20, 3)
+    B = rng.standard_normal(20)
+    junk = A + np.triu(rng.standard_normal((20, 20)))  # upper triangle and diagonal ignored
+    assert np.array_equal(oracle.solve(A, B), oracle.solve(junk, B))
+    low = np.tril(A, -1)
+    assert np.linalg.norm((low - low.T) @ oracle.solve(A, B) - B) < 1e-10
