@@ -43,9 +43,8 @@ size_t factor_ws_layout(int n, int b, FactorWs *ws, char *base);
 // Device workspace of skltlt_solve.
 struct SolveWs {
     int *q;      // row permutation (n)
-    double *Y;   // P B, then L^{-1} P B (n x nrhs, ld)
-    double *U;   // T^{-1} ..., then the solution before the inverse permutation
-    unsigned *flags; // per-block completion words of the single-launch solves (2 x blocks)
+    double *Y;   // P B and later stages (n x nrhs, ld)
+    double *U;   // later stages, last the solution before the inverse permutation
     int ld;
     size_t bytes;
 };

@@ -15,6 +15,7 @@
 // Pfaffian: Pf(A) = det(P) * prod_i T[2i][2i+1] (definition in Sec. 1 with
 // Pf(B X B^T) = det(B) Pf(X), T of Sec. 1 / eq. (TvsS): T[2i][2i+1] = -t[2i]).
 #include "common.h"
+#include "pivot_walk.h"
 
 #include <cmath>
 
@@ -58,35 +59,41 @@ hipError_t launch_set_int(int *p, int v, hipStream_t s)
 // steps after block B are applied to a column (composition of
 // transpositions, last step innermost).  Block B covers steps
 // [B*b, min((B+1)*b, n-1)).
-constexpr int kPC = 8192; // pivots staged in LDS per chunk
 __global__ __launch_bounds__(256) void suffix_map_kernel(const int *__restrict__ ipiv, int n,
                                                          int b, int nblk,
                                                          int *__restrict__ gmap)
 {
-    // every thread walks all later pivots, so they are staged in LDS a chunk
-    // at a time (their load latency would otherwise serialize the walk)
-    __shared__ int sp[kPC];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int v = i;
-    if (i < n)
-        gmap[(size_t)(nblk - 1) * n + i] = v;
-    // steps c = n-2 down to b (blocks nblk-1 .. 1); pivot of step c is ipiv[c+1]
-    int B = nblk - 2;                  // the map of block B gets the steps of blocks > B
-    int next_store = (B + 1) * b;      // after applying step next_store, store gmap[B]
-    for (int hi = n - 2; hi >= b; hi -= kPC) {
-        const int lo = max(b, hi - kPC + 1);
+    // the steps c >= (B+1) b of the map of block B are the transpositions
+    // r = c + 1 >= (B+1) b + 1; one walk over r = n-1 .. b+1 takes a
+    // snapshot at each block boundary (chunks end on the boundaries)
+    __shared__ int sp[kWalkStage];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int i0 = (blockIdx.x * 4 + wave) * kWalkI;
+    const int imax = i0 + kWalkI - 1;
+    int v[kWalkI];
+#pragma unroll
+    for (int k = 0; k < kWalkI; ++k)
+        v[k] = i0 + k;
+    walk_store(v, i0, n, lane, gmap + (size_t)(nblk - 1) * n);
+    int B = nblk - 2;
+    int bnd = (B + 1) * b + 1; // lowest transposition of the map of block B
+    for (int hi = n - 1; hi >= b + 1; hi -= kWalkStage) {
+        const int lo = max(b + 1, hi - kWalkStage + 1);
         __syncthreads();
-        for (int c = lo + (int)threadIdx.x; c <= hi; c += blockDim.x)
-            sp[c - lo] = ipiv[c + 1];
+        walk_stage(ipiv, lo, hi, sp);
         __syncthreads();
-        for (int c = hi; c >= lo; --c) {
-            const int rr = c + 1, pp = sp[c - lo];
-            v = (v == rr) ? pp : ((v == pp) ? rr : v);
-            if (c == next_store) {
-                if (i < n)
-                    gmap[(size_t)B * n + i] = v;
+        for (int R = hi; R >= lo;) {
+            const int bot = max(max(lo, R - 63), bnd);
+            if (bot <= imax && i0 < n) {
+                const int pr = sp[max(R - lane, bot) - lo];
+                walk_chunk(v, i0, R, R - bot + 1, pr);
+            }
+            R = bot - 1;
+            if (bot == bnd) {
+                walk_store(v, i0, n, lane, gmap + (size_t)B * n);
                 --B;
-                next_store -= b;
+                bnd -= b;
             }
         }
     }
@@ -181,7 +188,8 @@ hipError_t launch_finalize(double *A, int lda, int n, int b, const int *ipiv,
     if (nblk <= 1)
         return hipSuccess;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(suffix_map_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ipiv, n, b,
+    hipLaunchKernelGGL(suffix_map_kernel, dim3((n + 4 * kWalkI - 1) / (4 * kWalkI)), dim3(256), 0,
+                       s, ipiv, n, b,
                        nblk, ws.gmap);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)

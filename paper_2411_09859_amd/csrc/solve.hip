@@ -19,6 +19,7 @@
 // L is read where the factorization left it: L[i][j] = LT[i][j-1] for
 // i > j >= 1, L[i][0] = 0 for i > 0, unit diagonal.
 #include "common.h"
+#include "pivot_walk.h"
 
 namespace skl {
 
@@ -32,29 +33,34 @@ __device__ __forceinline__ double lval(const double *__restrict__ LT, int lda, i
     return (j >= 1) ? LT[(size_t)(j - 1) * lda + i] : 0.0;
 }
 
-// q[i] = image of i under the transpositions applied last to first.  The
-// pivots are staged in LDS a chunk at a time (every thread walks all of
-// them, so their latency would otherwise serialize the walk).
-constexpr int kPC = 8192;
+// q[i] = image of i under the transpositions applied last to first (one
+// wave per kWalkI indices, pivots staged in LDS).
 __global__ __launch_bounds__(256) void perm_map_kernel(const int *__restrict__ ipiv, int n,
                                                        int *__restrict__ q)
 {
-    __shared__ int sp[kPC];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int v = i;
-    for (int hi = n - 1; hi >= 1; hi -= kPC) {
-        const int lo = max(1, hi - kPC + 1);
+    __shared__ int sp[kWalkStage];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int i0 = (blockIdx.x * 4 + wave) * kWalkI;
+    const int imax = i0 + kWalkI - 1;
+    int v[kWalkI];
+#pragma unroll
+    for (int k = 0; k < kWalkI; ++k)
+        v[k] = i0 + k;
+    for (int hi = n - 1; hi >= 1; hi -= kWalkStage) {
+        const int lo = max(1, hi - kWalkStage + 1);
         __syncthreads();
-        for (int r = lo + (int)threadIdx.x; r <= hi; r += blockDim.x)
-            sp[r - lo] = ipiv[r];
+        walk_stage(ipiv, lo, hi, sp);
         __syncthreads();
-        for (int r = hi; r >= lo; --r) {
-            const int p = sp[r - lo];
-            v = (v == r) ? p : ((v == p) ? r : v);
+        if (i0 < n) {
+            for (int R = min(hi, imax); R >= lo; R -= 64) {
+                const int len = min(64, R - lo + 1);
+                const int pr = sp[max(R - lane, lo) - lo];
+                walk_chunk(v, i0, R, len, pr);
+            }
         }
     }
-    if (i < n)
-        q[i] = v;
+    walk_store(v, i0, n, lane, q);
 }
 
 // Y[i][k] = B[q[i]][k] (gather) or B[q[i]][k] = Y[i][k] (scatter).
@@ -296,16 +302,20 @@ __global__ __launch_bounds__(256) void trsv_upper_block_kernel(const double *__r
 
 // ---- single-launch triangular solves ---------------------------------------
 // One workgroup per block of kFB rows (all resident: cooperative launch).
-// Workgroup b takes the contributions of the other blocks as soon as each of
-// them has published its solution (a flag word per block, written after the
-// block's values are device-visible), then solves its own diagonal block in
-// one wave per right-hand side (lane = row, the pivot value broadcast with
-// readlane, no barriers) and publishes.  The chain between consecutive blocks
-// is one flag round trip plus a 64-step in-register solve; everything else
-// (reading L once, 8 n^2 / 2 bytes) overlaps with it.  Bounded waits: a block
-// that never appears poisons the result with NaN instead of hanging.
+// The solution goes to a separate array that is filled beforehand with a
+// "pending" marker, a signaling NaN, which arithmetic never produces; a
+// value other than the marker is final.  Workgroup b takes the contributions
+// of the other blocks as their values appear, then solves its own diagonal
+// block in one wave per right-hand side (lane = row, the pivot value
+// broadcast with readlane, no barriers) and stores it.  A consumer polls the
+// values it needs directly, so the chain between consecutive blocks is one
+// store-to-load round trip plus the 64-step in-register solve; everything
+// else (reading L once, 8 n^2 / 2 bytes) overlaps with it.  Bounded waits: a
+// block that never appears poisons the result with a quiet NaN instead of
+// hanging.
 constexpr int kFB = 64;
 constexpr long kSolveSpin = 1L << 22;
+constexpr unsigned long long kPending = 0xfff7a5a5a5a5a5a5ull;
 
 __device__ __forceinline__ double ld_dev(const double *p)
 {
@@ -315,6 +325,10 @@ __device__ __forceinline__ void st_dev(double *p, double v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ bool is_pending(double x)
+{
+    return (unsigned long long)__double_as_longlong(x) == kPending;
+}
 __device__ __forceinline__ double readlane_f64(double v, int l)
 {
     const long long b = __double_as_longlong(v);
@@ -322,24 +336,56 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-__device__ __forceinline__ bool wait_flag(const unsigned *f, unsigned stamp)
+
+__global__ void fill_pending_kernel(double *__restrict__ p, size_t count)
 {
-    long spins = 0;
-    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != stamp) {
-        if (++spins > kSolveSpin)
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        p[i] = __longlong_as_double((long long)kPending);
+}
+
+// Loads the 16 x NR values z[k][jj] = X[k * ldx + idx(jj)] of another block
+// once none of them is pending (false if the wait runs out).
+template <int NR, class Idx>
+__device__ __forceinline__ bool poll16(const double *X, int ldx, Idx idx, double (&z)[NR][16])
+{
+    for (long spins = 0;; ++spins) {
+        bool pend = false;
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                z[k][jj] = ld_dev(&X[(size_t)k * ldx + idx(jj)]);
+                pend |= is_pending(z[k][jj]);
+            }
+        if (__ballot(pend) == 0)
+            return true;
+        if (spins > kSolveSpin)
             return false;
         __builtin_amdgcn_s_sleep(1);
     }
-    return true;
+}
+// Per lane: the value at p once no lane's value is pending.
+__device__ __forceinline__ bool poll_lane(const double *p, double *z)
+{
+    for (long spins = 0;; ++spins) {
+        *z = ld_dev(p);
+        if (__ballot(is_pending(*z)) == 0)
+            return true;
+        if (spins > kSolveSpin)
+            return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
 }
 
-// Forward: Y[b] := L_bb^{-1} (Y[b] - sum_{c<b} L_bc Y[c]), blocks ascending.
-// Wave w takes columns 16w .. 16w+15 of every earlier block (lane = row).
+// Forward: Z[b] := L_bb^{-1} (Y[b] - sum_{c<b} L_bc Z[c]), blocks ascending.
+// Wave w takes columns 16w .. 16w+15 of every earlier block but the last
+// (lane = row); the last one is on the critical path and taken by the waves
+// that solve, one per right-hand side.
 template <int NR>
 __global__ __launch_bounds__(256) void trsv_lower_sf_kernel(const double *__restrict__ LT, int lda,
-                                                            int n, double *__restrict__ Y, int ldy,
-                                                            unsigned *__restrict__ flags,
-                                                            unsigned stamp)
+                                                            int n, const double *__restrict__ Y,
+                                                            int ldy, double *__restrict__ Z, int ldz)
 {
     __shared__ double Ld[kFB][kFB + 1]; // Ld[j][i] = L[r0+i][r0+j]
     __shared__ double part[4][NR][kFB];
@@ -358,21 +404,19 @@ __global__ __launch_bounds__(256) void trsv_lower_sf_kernel(const double *__rest
     for (int k = 0; k < NR; ++k)
         acc[k] = 0.0;
     bool ok = true;
-    // every earlier block but the last: all waves, in the background
     for (int c = 0; c + 1 < b && ok; ++c) {
         const int c0 = c * kFB + wave * 16;
         double l[16];
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj)
             l[jj] = lval(LT, lda, row, c0 + jj); // row >= r0 > column: below the diagonal
-        ok = wait_flag(&flags[c], stamp);
-        if (!ok)
-            break;
+        double z[NR][16];
+        ok = poll16<NR>(Z, ldz, [&](int jj) { return c0 + jj; }, z);
 #pragma unroll
         for (int k = 0; k < NR; ++k)
 #pragma unroll
             for (int jj = 0; jj < 16; ++jj)
-                acc[k] += l[jj] * ld_dev(&Y[(size_t)k * ldy + c0 + jj]);
+                acc[k] += l[jj] * z[k][jj];
     }
     if (!ok)
         fail = 1;
@@ -382,22 +426,23 @@ __global__ __launch_bounds__(256) void trsv_lower_sf_kernel(const double *__rest
     __syncthreads();
     if (wave < NR) {
         const int k = wave;
+        bool bad = fail != 0;
         double y = 0.0;
         if (lane < h)
             y = Y[(size_t)k * ldy + r0 + lane] - ((part[0][k][lane] + part[1][k][lane]) +
                                                   (part[2][k][lane] + part[3][k][lane]));
-        // the block just before, on the critical path: its L rows are read
-        // before waiting, its solution with one load per lane, then applied
-        // column by column with the value broadcast by readlane
+        // the block just before: its L rows are read before waiting, its
+        // solution with one load per lane, then applied column by column
+        // with the value broadcast by readlane
         if (b >= 1) {
             const int c0 = (b - 1) * kFB;
             double l[kFB];
 #pragma unroll
             for (int jj = 0; jj < kFB; ++jj)
                 l[jj] = lval(LT, lda, row, c0 + jj);
-            if (!wait_flag(&flags[b - 1], stamp))
-                fail = 1;
-            const double zv = ld_dev(&Y[(size_t)k * ldy + c0 + lane]);
+            double zv;
+            if (!poll_lane(&Z[(size_t)k * ldz + c0 + lane], &zv))
+                bad = true;
 #pragma unroll
             for (int jj = 0; jj < kFB; ++jj)
                 y -= l[jj] * readlane_f64(zv, jj);
@@ -407,25 +452,21 @@ __global__ __launch_bounds__(256) void trsv_lower_sf_kernel(const double *__rest
             if (lane > j)
                 y -= Ld[j][lane] * zj;
         }
-        if (fail)
+        if (bad)
             y = __longlong_as_double(0x7ff8000000000000ll);
         if (lane < h)
-            st_dev(&Y[(size_t)k * ldy + r0 + lane], y);
-        __builtin_amdgcn_s_waitcnt(0x0F70); // this wave's stores are complete
+            st_dev(&Z[(size_t)k * ldz + r0 + lane], y);
     }
-    __syncthreads();
-    if (tid == 0)
-        __hip_atomic_store(&flags[b], stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Backward: U[b] := L_bb^{-T} (U[b] - sum_{c>b} L_cb^T U[c]), blocks
-// descending.  Wave w takes rows 16w .. 16w+15 of every later block; lane =
-// column of block b (the 16 rows of one column are one 128-byte line).
+// Backward: X[b] := L_bb^{-T} (U[b] - sum_{c>b} L_cb^T X[c]), blocks
+// descending.  Wave w takes rows 16w .. 16w+15 of every later block but the
+// nearest; lane = column of block b (the 16 rows of one column are one
+// 128-byte line).
 template <int NR>
 __global__ __launch_bounds__(256) void trsv_upper_sf_kernel(const double *__restrict__ LT, int lda,
-                                                            int n, double *__restrict__ U, int ldu,
-                                                            unsigned *__restrict__ flags,
-                                                            unsigned stamp)
+                                                            int n, const double *__restrict__ U,
+                                                            int ldu, double *__restrict__ X, int ldx)
 {
     __shared__ double Ld[kFB][kFB + 1]; // Ld[j][i] = L[r0+i][r0+j]
     __shared__ double part[4][NR][kFB];
@@ -445,7 +486,6 @@ __global__ __launch_bounds__(256) void trsv_upper_sf_kernel(const double *__rest
     for (int k = 0; k < NR; ++k)
         acc[k] = 0.0;
     bool ok = true;
-    // every later block but the nearest: all waves, in the background
     for (int c = nb - 1; c > b + 1 && ok; --c) {
         const int i0 = c * kFB + wave * 16;
         const int cnt = min(16, n - i0); // rows of this slice that exist
@@ -457,14 +497,13 @@ __global__ __launch_bounds__(256) void trsv_upper_sf_kernel(const double *__rest
             const double lv = lval(LT, lda, min(i0 + ii, n - 1), col);
             l[ii] = (ii < cnt) ? lv : 0.0;
         }
-        ok = wait_flag(&flags[c], stamp);
-        if (!ok)
-            break;
+        double x[NR][16];
+        ok = poll16<NR>(X, ldx, [&](int ii) { return min(i0 + ii, n - 1); }, x);
 #pragma unroll
         for (int k = 0; k < NR; ++k)
 #pragma unroll
             for (int ii = 0; ii < 16; ++ii)
-                acc[k] += l[ii] * ld_dev(&U[(size_t)k * ldu + min(i0 + ii, n - 1)]);
+                acc[k] += l[ii] * x[k][ii];
     }
     if (!ok)
         fail = 1;
@@ -474,12 +513,13 @@ __global__ __launch_bounds__(256) void trsv_upper_sf_kernel(const double *__rest
     __syncthreads();
     if (wave < NR) {
         const int k = wave;
+        bool bad = fail != 0;
         double y = 0.0;
         if (lane < h)
             y = U[(size_t)k * ldu + r0 + lane] - ((part[0][k][lane] + part[1][k][lane]) +
                                                   (part[2][k][lane] + part[3][k][lane]));
-        // the block just after, on the critical path (lane = column of
-        // block b; row i of block b+1 of that column, read before waiting)
+        // the block just after (lane = column of block b; row i of block
+        // b+1 of that column, read before waiting)
         if (b + 1 < nb) {
             const int i0 = (b + 1) * kFB;
             const int cnt = min(kFB, n - i0);
@@ -489,9 +529,9 @@ __global__ __launch_bounds__(256) void trsv_upper_sf_kernel(const double *__rest
                 const double lv = lval(LT, lda, min(i0 + ii, n - 1), col);
                 l[ii] = (ii < cnt) ? lv : 0.0;
             }
-            if (!wait_flag(&flags[b + 1], stamp))
-                fail = 1;
-            const double xv = ld_dev(&U[(size_t)k * ldu + min(i0 + lane, n - 1)]);
+            double xv;
+            if (!poll_lane(&X[(size_t)k * ldx + min(i0 + lane, n - 1)], &xv))
+                bad = true;
 #pragma unroll
             for (int ii = 0; ii < kFB; ++ii)
                 y -= l[ii] * readlane_f64(xv, ii);
@@ -502,25 +542,25 @@ __global__ __launch_bounds__(256) void trsv_upper_sf_kernel(const double *__rest
             if (lane < j)
                 y -= Ld[lane][j] * xj;
         }
-        if (fail)
+        if (bad)
             y = __longlong_as_double(0x7ff8000000000000ll);
         if (lane < h)
-            st_dev(&U[(size_t)k * ldu + r0 + lane], y);
-        __builtin_amdgcn_s_waitcnt(0x0F70);
+            st_dev(&X[(size_t)k * ldx + r0 + lane], y);
     }
-    __syncthreads();
-    if (tid == 0)
-        __hip_atomic_store(&flags[b], stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Launch one single-launch solve for up to 4 right-hand sides; returns
+// Launch one single-launch solve for up to 4 right-hand sides (In -> Out,
+// Out filled with the pending marker); returns
 // hipErrorCooperativeLaunchTooLarge (or another error) when it cannot run.
-static hipError_t launch_sf(bool lower, int nr, const double *LT, int lda, int n, double *Y,
-                            int ldy, unsigned *flags, unsigned stamp, hipStream_t s)
+static hipError_t launch_sf(bool lower, int nr, const double *LT, int lda, int n, const double *In,
+                            double *Out, int ld, hipStream_t s)
 {
     const int nb = (n + kFB - 1) / kFB;
-    void *args[] = {(void *)&LT, (void *)&lda, (void *)&n, (void *)&Y,
-                    (void *)&ldy, (void *)&flags, (void *)&stamp};
+    const size_t cnt = (size_t)ld * nr;
+    hipLaunchKernelGGL(fill_pending_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                       Out, cnt);
+    void *args[] = {(void *)&LT, (void *)&lda, (void *)&n, (void *)&In,
+                    (void *)&ld, (void *)&Out, (void *)&ld};
     const void *fn = nullptr;
     switch (nr) {
     case 1: fn = lower ? (const void *)trsv_lower_sf_kernel<1> : (const void *)trsv_upper_sf_kernel<1>; break;
@@ -531,19 +571,30 @@ static hipError_t launch_sf(bool lower, int nr, const double *LT, int lda, int n
     return hipLaunchCooperativeKernel(fn, dim3(nb), dim3(256), args, 0, s);
 }
 
-// Whether every block of the single-launch solve can be resident at once.
-static bool sf_fits(int n)
+// Whether every block of the single-launch solves for nr right-hand sides
+// can be resident at once.
+static bool sf_fits(int n, int nr)
 {
-    static int per_cu = -1;
-    if (per_cu < 0) {
-        int pc = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &pc, (const void *)trsv_upper_sf_kernel<4>, 256, 0) != hipSuccess)
-            pc = 0;
-        per_cu = pc;
+    static int per_cu[5] = {-1, -1, -1, -1, -1};
+    if (nr < 1 || nr > 4)
+        return false;
+    if (per_cu[nr] < 0) {
+        const void *lo = nullptr, *up = nullptr;
+        switch (nr) {
+        case 1: lo = (const void *)trsv_lower_sf_kernel<1>; up = (const void *)trsv_upper_sf_kernel<1>; break;
+        case 2: lo = (const void *)trsv_lower_sf_kernel<2>; up = (const void *)trsv_upper_sf_kernel<2>; break;
+        case 3: lo = (const void *)trsv_lower_sf_kernel<3>; up = (const void *)trsv_upper_sf_kernel<3>; break;
+        default: lo = (const void *)trsv_lower_sf_kernel<4>; up = (const void *)trsv_upper_sf_kernel<4>; break;
+        }
+        int a = 0, c = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, lo, 256, 0) != hipSuccess)
+            a = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, up, 256, 0) != hipSuccess)
+            c = 0;
+        per_cu[nr] = a < c ? a : c;
     }
     const int nb = (n + kFB - 1) / kFB;
-    return per_cu > 0 && (long)nb <= (long)per_cu * device_cu_count();
+    return per_cu[nr] > 0 && (long)nb <= (long)per_cu[nr] * device_cu_count();
 }
 
 static const size_t kSolveLds = sizeof(double) * (size_t)(kSB * kSBP + kRC * kSB);
@@ -569,7 +620,6 @@ size_t solve_ws_layout(int n, int nrhs, SolveWs *ws, char *base)
     w.q = (int *)take(sizeof(int) * (size_t)w.ld);
     w.Y = (double *)take(sizeof(double) * (size_t)w.ld * (size_t)(nrhs > 0 ? nrhs : 1));
     w.U = (double *)take(sizeof(double) * (size_t)w.ld * (size_t)(nrhs > 0 ? nrhs : 1));
-    w.flags = (unsigned *)take(sizeof(unsigned) * 2 * (size_t)((w.ld + kFB - 1) / kFB));
     w.bytes = off;
     if (ws)
         *ws = w;
@@ -579,22 +629,25 @@ size_t solve_ws_layout(int n, int nrhs, SolveWs *ws, char *base)
 hipError_t launch_solve(int n, int nrhs, const double *LT, int lda, const double *t,
                         const int *ipiv, double *B, int ldb, const SolveWs &ws, hipStream_t s)
 {
+    // single-launch path: P B -> Y, L^{-1} Y -> U, T^{-1} U -> Y, L^{-T} Y -> U
+    // block path:         P B -> Y, L^{-1} in place, T^{-1} Y -> U, L^{-T} in place
+    // then the solution in U goes back through P^T
     (void)hipGetLastError(); // report these launches only
     const int ld = ws.ld;
     const size_t tot = (size_t)n * nrhs;
     const unsigned pgrid = (unsigned)((tot + 255) / 256);
-    const bool sf = nrhs <= 4 && sf_fits(n);
-    const int nb = (n + kFB - 1) / kFB;
-    if (sf) {
-        hipError_t e = launch_fill_zero(ws.flags, sizeof(unsigned) * 2 * (size_t)nb, s);
-        if (e != hipSuccess)
-            return e;
-    }
-    hipLaunchKernelGGL(perm_map_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ipiv, n, ws.q);
+    const bool sf = nrhs <= 4 && sf_fits(n, nrhs);
+    hipLaunchKernelGGL(perm_map_kernel, dim3((n + 4 * kWalkI - 1) / (4 * kWalkI)), dim3(256), 0,
+                       s, ipiv, n, ws.q);
     hipLaunchKernelGGL(permute_rows_kernel, dim3(pgrid), dim3(256), 0, s, B, ldb, ws.Y, ld,
                        (const int *)ws.q, n, nrhs, 0);
     if (sf) {
-        hipError_t e = launch_sf(true, nrhs, LT, lda, n, ws.Y, ld, ws.flags, 1u, s);
+        hipError_t e = launch_sf(true, nrhs, LT, lda, n, ws.Y, ws.U, ld, s);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(tridiag_skew_solve_kernel, dim3(2 * nrhs), dim3(256), 0, s, t, n,
+                           (const double *)ws.U, ld, ws.Y, ld, nrhs);
+        e = launch_sf(false, nrhs, LT, lda, n, ws.Y, ws.U, ld, s);
         if (e != hipSuccess)
             return e;
     } else {
@@ -607,14 +660,8 @@ hipError_t launch_solve(int n, int nrhs, const double *LT, int lda, const double
                 hipLaunchKernelGGL(lower_update_kernel, dim3((below + 255) / 256), dim3(256), 0, s,
                                    LT, lda, n, c0, bs, ws.Y, ld, nrhs);
         }
-    }
-    hipLaunchKernelGGL(tridiag_skew_solve_kernel, dim3(2 * nrhs), dim3(256), 0, s, t, n,
-                       (const double *)ws.Y, ld, ws.U, ld, nrhs);
-    if (sf) {
-        hipError_t e = launch_sf(false, nrhs, LT, lda, n, ws.U, ld, ws.flags + nb, 1u, s);
-        if (e != hipSuccess)
-            return e;
-    } else {
+        hipLaunchKernelGGL(tridiag_skew_solve_kernel, dim3(2 * nrhs), dim3(256), 0, s, t, n,
+                           (const double *)ws.Y, ld, ws.U, ld, nrhs);
         const int nbs = (n + kSB - 1) / kSB;
         for (int B_ = nbs - 1; B_ >= 0; --B_) {
             const int c0 = B_ * kSB, bs = min(kSB, n - c0);
