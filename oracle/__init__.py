@@ -34,6 +34,8 @@ MUTATIONS = {
     "l_from_upper": 6,
     "last_index_ties": 7,
     "wrong_l_column": 8,
+    "partial_update_sign": 9,
+    "partial_unscaled_l": 10,
 }
 
 
@@ -60,6 +62,9 @@ def _load():
         lib.oracle_ltlt.restype = ctypes.c_int
         lib.oracle_pfaffian.argtypes = [ctypes.c_int, dp, ip, dp, ip, ctypes.c_int]
         lib.oracle_pfaffian.restype = ctypes.c_int
+        lib.oracle_ltlt_partial.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ip,
+                                            ctypes.c_int, ctypes.c_int]
+        lib.oracle_ltlt_partial.restype = ctypes.c_int
         lib.oracle_pack.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int]
         lib.oracle_pack.restype = ctypes.c_int
         _lib = lib
@@ -96,6 +101,26 @@ def ltlt(A: np.ndarray, max_steps: int = -1, nthreads: int = 0, mutation: int | 
     if rc != 0:
         raise ValueError(f"oracle_ltlt failed with status {rc}")
     return {"X": X, "L": L, "t": t[: max(n - 1, 0)], "ipiv": ipiv[:n]}
+
+
+def ltlt_partial(A: np.ndarray, nthreads: int = 0, mutation: int | str = 0):
+    """The Pfaffian-only reduction (one pivot and one rank-2 Schur complement
+    per pair of columns) of the skew matrix whose strict lower triangle is
+    ``A``.  Returns ``t`` (tau of the even steps, 0 at odd positions) and
+    ``ipiv`` (exchanges at the even steps only); :func:`pfaffian` of the two
+    gives Pf(A)."""
+    if isinstance(mutation, str):
+        mutation = MUTATIONS[mutation]
+    A = np.asfortranarray(A, dtype=np.float64)
+    n = A.shape[0]
+    assert A.shape == (n, n)
+    t = np.zeros(max(n - 1, 1), dtype=np.float64)
+    ipiv = np.zeros(max(n, 1), dtype=np.int32)
+    rc = _load().oracle_ltlt_partial(n, _dp(A), max(n, 1), _dp(t), _ip(ipiv), int(nthreads),
+                                     int(mutation))
+    if rc != 0:
+        raise ValueError(f"oracle_ltlt_partial failed with status {rc}")
+    return {"t": t[: max(n - 1, 0)], "ipiv": ipiv[:n]}
 
 
 def pfaffian(n: int, t: np.ndarray, ipiv: np.ndarray, mutation: int | str = 0):

@@ -60,7 +60,9 @@ enum {
     MUT_PF_PAPER_PRODUCT = 5, /* Pfaffian = prod t[2i] (no T sign, no P)   */
     MUT_L_FROM_UPPER = 6,     /* l taken from the upper triangle (-x)      */
     MUT_LAST_INDEX_TIES = 7,  /* iamax keeps the last of equal magnitudes  */
-    MUT_WRONG_L_COLUMN = 8    /* l stored one column too far right         */
+    MUT_WRONG_L_COLUMN = 8,   /* l stored one column too far right         */
+    MUT_PARTIAL_UPDATE_SIGN = 9, /* partial: X += c l^T - l c^T          */
+    MUT_PARTIAL_UNSCALED_L = 10  /* partial: l = x (not divided by tau)     */
 };
 
 int oracle_ltlt(int n, const double *A, int lda, double *X, double *L,
@@ -193,6 +195,119 @@ int oracle_ltlt(int n, const double *A, int lda, double *X, double *L,
 
     free(l);
     free(x);
+    return 0;
+}
+
+/* The Pfaffian-only reduction (Wimmer's algorithm as described in Sec. 3.5.2,
+ * Notes, and Sec. 3.6.5, Note): the two-step right-looking algorithm with the
+ * second Gauss transform of each pair (l43) and its tau (tau32) skipped.
+ * Per pair of columns k, k+1 (k even):
+ *   - iamax over X[k+1:n, k] and the symmetric exchange k+1 <-> p (Sec. 3.7);
+ *   - tau = X[k+1][k]; l = X[k+2:n, k] / tau (0 if tau = 0);
+ *   - c = X[k+2:n, k+1], the pair's second column, which the pair's own
+ *     transform leaves unchanged (chi22 = 0, Sec. 3.5.2);
+ *   - X[k+2:n, k+2:n] += l c^T - c l^T: the Schur complement of the 2 x 2
+ *     block [[0, -tau], [tau, 0]], since Pf of that block is -tau and
+ *     Pf(A) = Pf(block) Pf(complement) for a block-triangular congruence.
+ * Pf(A) = det(P) prod_k (-tau_k) over the even k, as for the full
+ * factorization. */
+int oracle_ltlt_partial(int n, const double *A, int lda, double *t, int *ipiv,
+                        int nthreads, int mutation)
+{
+    if (n < 0 || lda < (n > 1 ? n : 1) || (n > 0 && (!A || !ipiv)))
+        return -1;
+    if (n > 1 && !t)
+        return -1;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    if (n == 0)
+        return 0;
+    double *X = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+    double *l = (double *)malloc(sizeof(double) * (size_t)n);
+    double *c = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!X || !l || !c) {
+        free(X);
+        free(l);
+        free(c);
+        return -3;
+    }
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < n; ++i) {
+            double v;
+            if (i > j)
+                v = A[(size_t)j * lda + i];
+            else if (i < j)
+                v = -A[(size_t)i * lda + j];
+            else
+                v = 0.0;
+            if (!isfinite(v)) {
+                free(X);
+                free(l);
+                free(c);
+                return -2;
+            }
+            X_(i, j) = v;
+        }
+    }
+    ipiv[0] = 0;
+    for (int i = 1; i < n; ++i)
+        ipiv[i] = i;
+    for (int k = 0; k + 1 < n; ++k)
+        t[k] = 0.0;
+
+    for (int k = 0; k + 1 < n; k += 2) {
+        const int r = k + 1;
+        int p = r;
+        double amax = fabs(X_(r, k));
+        for (int i = r + 1; i < n; ++i) {
+            double a = fabs(X_(i, k));
+            if (a > amax) {
+                amax = a;
+                p = i;
+            }
+        }
+        ipiv[r] = p;
+        if (p != r) {
+            for (int j = 0; j < n; ++j) {
+                double s = X_(r, j);
+                X_(r, j) = X_(p, j);
+                X_(p, j) = s;
+            }
+            for (int i = 0; i < n; ++i) {
+                double s = X_(i, r);
+                X_(i, r) = X_(i, p);
+                X_(i, p) = s;
+            }
+        }
+        const double tau = X_(r, k);
+        t[k] = tau;
+        for (int i = r + 1; i < n; ++i) {
+            if (mutation == MUT_PARTIAL_UNSCALED_L)
+                l[i] = X_(i, k);
+            else
+                l[i] = (tau != 0.0) ? X_(i, k) / tau : 0.0;
+            c[i] = X_(i, r);
+        }
+        const double sg = (mutation == MUT_PARTIAL_UPDATE_SIGN) ? -1.0 : 1.0;
+        /* Schur complement of the pair: rows and columns k+2 .. n-1 */
+#pragma omp parallel for schedule(static)
+        for (int j = r + 1; j < n; ++j) {
+            const double cj = c[j], lj = l[j];
+            for (int i = r + 1; i < n; ++i)
+                X_(i, j) = X_(i, j) + sg * (l[i] * cj - c[i] * lj);
+        }
+        for (int i = r + 1; i < n; ++i) {
+            X_(i, k) = 0.0;
+            X_(k, i) = 0.0;
+        }
+    }
+    free(X);
+    free(l);
+    free(c);
     return 0;
 }
 

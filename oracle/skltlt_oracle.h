@@ -32,6 +32,16 @@ int oracle_ltlt(int n, const double *A, int lda, double *X, double *L,
 int oracle_pfaffian(int n, const double *t, const int *ipiv,
                     double *log_abs_pf, int *sign, int mutation);
 
+/* The Pfaffian-only ("partial") reduction: one pivot and one Gauss transform
+ * per PAIR of columns, the second transform of each pair and its tau never
+ * formed.  Same input as oracle_ltlt.
+ *   t    (out, n-1): t[k] = tau of the pivot step k for even k, 0 for odd k.
+ *   ipiv (out, n): ipiv[k+1] = pivot row of step k for even k; every other
+ *        entry is its own index (no exchange).
+ * Pf(A) then follows from oracle_pfaffian(n, t, ipiv, ...). */
+int oracle_ltlt_partial(int n, const double *A, int lda, double *t, int *ipiv,
+                        int nthreads, int mutation);
+
 /* Writes t and L into the strict lower triangle of Aout in the packed
  * in-place layout (t on the first subdiagonal, L[i][j+1] at (i, j)). */
 int oracle_pack(int n, const double *L, const double *t, double *Aout,

@@ -254,9 +254,134 @@ def test_pins_pass_on_oracle():
     assert _pin_failures("none") == []
 
 
-@pytest.mark.parametrize("mutation", [m for m in oracle.MUTATIONS if m != "none"])
+@pytest.mark.parametrize("mutation", [m for m in oracle.MUTATIONS
+                                      if m != "none" and not m.startswith("partial_")])
 def test_planted_mistake_is_caught(mutation):
     assert _pin_failures(mutation), f"mutation {mutation} escaped every pin"
+
+
+# ------------------------------------------- Pfaffian-only ("partial") reduction
+# Wimmer's algorithm (Sec. 3.5.2 Notes, Sec. 3.6.5 Note): one pivot and one
+# rank-2 Schur complement per pair of columns.  Pinned by the Pfaffian's
+# definition, closed forms, and pivots recomputed from Schur complements
+# formed with a dense library solve.
+def partial_pf(A, mutation=0):
+    n = A.shape[0]
+    res = oracle.ltlt_partial(A, mutation=mutation)
+    la, sg = oracle.pfaffian(n, res["t"], res["ipiv"])
+    return res, (0.0 if sg == 0 else sg * math.exp(la))
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 8, 10])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_partial_pf_brute_force(n, seed):
+    A = inputs.skew_normal(n, seed)
+    assert partial_pf(A)[1] == pytest.approx(ck.pf_expand(A), rel=1e-12)
+
+
+def test_partial_4x4_closed_form():
+    rng = np.random.default_rng(6)
+    for _ in range(20):
+        X = ck.full_skew(rng.standard_normal((4, 4)))
+        want = X[0, 1] * X[2, 3] - X[0, 2] * X[1, 3] + X[0, 3] * X[1, 2]
+        assert partial_pf(X)[1] == pytest.approx(want, rel=1e-12)
+
+
+@pytest.mark.parametrize("n", [2, 16, 64, 256])
+def test_partial_permuted_block_diagonal(n):
+    """Pf(Q diag([[0,a_i],[-a_i,0]]) Q^T) = det(Q) prod a_i."""
+    rng = np.random.default_rng(n + 1)
+    a = rng.uniform(0.5, 2.0, n // 2) * rng.choice([-1.0, 1.0], n // 2)
+    D = np.zeros((n, n))
+    for i in range(n // 2):
+        D[2 * i, 2 * i + 1], D[2 * i + 1, 2 * i] = a[i], -a[i]
+    q = rng.permutation(n)
+    X = D[np.ix_(q, q)]
+    want_sign = ck.perm_sign(q) * int(np.prod(np.sign(a)))
+    want_log = float(np.sum(np.log(np.abs(a))))
+    res = oracle.ltlt_partial(np.tril(X, -1))
+    la, sg = oracle.pfaffian(n, res["t"], res["ipiv"])
+    assert sg == want_sign
+    assert la == pytest.approx(want_log, rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("n,gen", [(64, "normal"), (200, "normal"), (128, "graded")])
+def test_partial_agrees_with_full_factorization(n, gen):
+    A = inputs.skew_normal(n, 31) if gen == "normal" else inputs.skew_graded(n, 31)
+    f = oracle.ltlt(A)
+    lf, sf = oracle.pfaffian(n, f["t"], f["ipiv"])
+    p = oracle.ltlt_partial(A)
+    lp, sp = oracle.pfaffian(n, p["t"], p["ipiv"])
+    assert sp == sf
+    assert lp == pytest.approx(lf, rel=1e-11)
+    # same first pivot (both search column 0 of A), exchanges only at even steps
+    assert p["ipiv"][1] == f["ipiv"][1]
+    assert np.array_equal(p["ipiv"][2::2], np.arange(2, n, 2))
+    assert np.all(p["ipiv"] >= np.arange(n))
+    assert np.all(p["t"][1::2] == 0.0)
+
+
+def _schur_pivots(A, ipiv, upto):
+    """Pivots recomputed without the oracle's arithmetic: for each pair k, the
+    leading k x k block of A permuted by the earlier exchanges is eliminated
+    with a dense solve; the pivot is the first largest entry of the Schur
+    complement's first column below its top."""
+    X = ck.full_skew(A)
+    n = X.shape[0]
+    q = np.arange(n)
+    got = []
+    for k in range(0, upto, 2):
+        B = X[np.ix_(q, q)]
+        if k == 0:
+            S = B
+        else:
+            S = B[k:, k:] - B[k:, :k] @ np.linalg.solve(B[:k, :k], B[:k, k:])
+        col = np.abs(S[1:, 0])
+        p = k + 1 + int(np.argmax(col))
+        got.append(p)
+        r = k + 1
+        q[r], q[p] = q[p], q[r]
+    return got
+
+
+def test_partial_pivots_from_schur_complements():
+    n = 40
+    A = inputs.skew_normal(n, 5)
+    res = oracle.ltlt_partial(A)
+    assert list(res["ipiv"][1:n:2][: n // 2 - 1]) == _schur_pivots(A, res["ipiv"], n - 2)
+
+
+def test_partial_exact_zeros_and_odd_order():
+    for n in (4, 16, 64):
+        for seed in range(3):
+            for A in (inputs.skew_odd_blocks(n, seed), inputs.skew_zero_line(n, seed)):
+                res = oracle.ltlt_partial(A)
+                assert oracle.pfaffian(n, res["t"], res["ipiv"])[1] == 0
+    res = oracle.ltlt_partial(inputs.skew_normal(7, 1))
+    assert oracle.pfaffian(7, res["t"], res["ipiv"]) == (-math.inf, 0)
+
+
+def _partial_pin_failures(mutation):
+    fails = []
+    for n, seed in ((6, 1), (8, 2), (10, 3)):
+        A = inputs.skew_normal(n, seed)
+        if not np.isclose(partial_pf(A, mutation)[1], ck.pf_expand(A), rtol=1e-10):
+            fails.append("brute")
+    n = 24
+    A = inputs.skew_normal(n, 9)
+    res = oracle.ltlt_partial(A, mutation=mutation)
+    if list(res["ipiv"][1:n:2][: n // 2 - 1]) != _schur_pivots(A, res["ipiv"], n - 2):
+        fails.append("schur pivots")
+    return fails
+
+
+def test_partial_pins_pass_on_oracle():
+    assert _partial_pin_failures("none") == []
+
+
+@pytest.mark.parametrize("mutation", [m for m in oracle.MUTATIONS if m.startswith("partial_")])
+def test_partial_planted_mistake_is_caught(mutation):
+    assert _partial_pin_failures(mutation), f"mutation {mutation} escaped every pin"
 
 
 # ------------------------------------------------------------ solve (oracle)
