@@ -105,6 +105,31 @@ int skltlt_pfaffian(int n, double *A, int lda, double *t, int *ipiv,
                     int precision, void *work, size_t work_bytes,
                     void *stream);
 
+/* Pfaffian only, by the "partial" reduction (Wimmer's algorithm: the
+ * two-step algorithm of Sec. 3.5.2 with the second Gauss transform of each
+ * pair and its tau skipped, Sec. 3.5.2 Notes; blocked with accumulated
+ * rank-2k updates, Sec. 3.6.5 Note).  Per pair of columns (k, k+1), k even:
+ * the pivot search and symmetric exchange on column k only (Sec. 3.7),
+ * tau_k = X[k+1][k], l = X[k+2:, k] / tau_k, c = X[k+2:, k+1], and the
+ * Schur complement X[k+2:, k+2:] += l c^T - c l^T.  Pf(A) = det(P) *
+ * prod_k (-tau_k) over the even k: the same value as skltlt_pfaffian in
+ * exact arithmetic, with half the pivot steps.
+ *   A (device)  read only (strict lower triangle, lda >= max(1, n)); no L
+ *               is formed.
+ *   t (device)  n-1 doubles: t[k] = tau_k for even k, 0 for odd k.
+ *   ipiv (device) n ints: ipiv[0] = 0, ipiv[k+1] = pivot row of step k for
+ *               even k, ipiv[k+2] = k+2 (no exchange) for the odd steps.
+ *   log_abs_pf, sign (device): as for skltlt_pfaffian.
+ *   block_size  0 = skltlt_default_block_size(n); an odd width is rounded
+ *               down to even (1 to 2).
+ *   precision, work, work_bytes, stream: as for skltlt_pfaffian (the same
+ *               workspace size).
+ * Errors as for skltlt_pfaffian. */
+int skltlt_pfaffian_partial(int n, const double *A, int lda, double *t,
+                            int *ipiv, double *log_abs_pf, int *sign,
+                            int block_size, int precision, void *work,
+                            size_t work_bytes, void *stream);
+
 /* Largest order handled by skltlt_batched. */
 int skltlt_batched_max_n(void);
 

@@ -63,7 +63,7 @@ def _load():
         lib.oracle_pfaffian.argtypes = [ctypes.c_int, dp, ip, dp, ip, ctypes.c_int]
         lib.oracle_pfaffian.restype = ctypes.c_int
         lib.oracle_ltlt_partial.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ip,
-                                            ctypes.c_int, ctypes.c_int]
+                                            ctypes.c_int, ctypes.c_int, ctypes.c_int]
         lib.oracle_ltlt_partial.restype = ctypes.c_int
         lib.oracle_pack.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int]
         lib.oracle_pack.restype = ctypes.c_int
@@ -103,12 +103,13 @@ def ltlt(A: np.ndarray, max_steps: int = -1, nthreads: int = 0, mutation: int | 
     return {"X": X, "L": L, "t": t[: max(n - 1, 0)], "ipiv": ipiv[:n]}
 
 
-def ltlt_partial(A: np.ndarray, nthreads: int = 0, mutation: int | str = 0):
+def ltlt_partial(A: np.ndarray, max_pairs: int = -1, nthreads: int = 0,
+                 mutation: int | str = 0):
     """The Pfaffian-only reduction (one pivot and one rank-2 Schur complement
     per pair of columns) of the skew matrix whose strict lower triangle is
     ``A``.  Returns ``t`` (tau of the even steps, 0 at odd positions) and
     ``ipiv`` (exchanges at the even steps only); :func:`pfaffian` of the two
-    gives Pf(A)."""
+    gives Pf(A).  ``max_pairs`` >= 0 stops after that many pairs."""
     if isinstance(mutation, str):
         mutation = MUTATIONS[mutation]
     A = np.asfortranarray(A, dtype=np.float64)
@@ -116,8 +117,8 @@ def ltlt_partial(A: np.ndarray, nthreads: int = 0, mutation: int | str = 0):
     assert A.shape == (n, n)
     t = np.zeros(max(n - 1, 1), dtype=np.float64)
     ipiv = np.zeros(max(n, 1), dtype=np.int32)
-    rc = _load().oracle_ltlt_partial(n, _dp(A), max(n, 1), _dp(t), _ip(ipiv), int(nthreads),
-                                     int(mutation))
+    rc = _load().oracle_ltlt_partial(n, _dp(A), max(n, 1), _dp(t), _ip(ipiv), int(max_pairs),
+                                     int(nthreads), int(mutation))
     if rc != 0:
         raise ValueError(f"oracle_ltlt_partial failed with status {rc}")
     return {"t": t[: max(n - 1, 0)], "ipiv": ipiv[:n]}

@@ -212,7 +212,7 @@ int oracle_ltlt(int n, const double *A, int lda, double *X, double *L,
  * Pf(A) = det(P) prod_k (-tau_k) over the even k, as for the full
  * factorization. */
 int oracle_ltlt_partial(int n, const double *A, int lda, double *t, int *ipiv,
-                        int nthreads, int mutation)
+                        int max_pairs, int nthreads, int mutation)
 {
     if (n < 0 || lda < (n > 1 ? n : 1) || (n > 0 && (!A || !ipiv)))
         return -1;
@@ -260,6 +260,8 @@ int oracle_ltlt_partial(int n, const double *A, int lda, double *t, int *ipiv,
         t[k] = 0.0;
 
     for (int k = 0; k + 1 < n; k += 2) {
+        if (max_pairs >= 0 && k / 2 >= max_pairs)
+            break;
         const int r = k + 1;
         int p = r;
         double amax = fabs(X_(r, k));

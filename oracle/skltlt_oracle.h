@@ -38,9 +38,10 @@ int oracle_pfaffian(int n, const double *t, const int *ipiv,
  *   t    (out, n-1): t[k] = tau of the pivot step k for even k, 0 for odd k.
  *   ipiv (out, n): ipiv[k+1] = pivot row of step k for even k; every other
  *        entry is its own index (no exchange).
+ *   max_pairs: < 0 for the whole reduction, else stop after that many pairs.
  * Pf(A) then follows from oracle_pfaffian(n, t, ipiv, ...). */
 int oracle_ltlt_partial(int n, const double *A, int lda, double *t, int *ipiv,
-                        int nthreads, int mutation);
+                        int max_pairs, int nthreads, int mutation);
 
 /* Writes t and L into the strict lower triangle of Aout in the packed
  * in-place layout (t on the first subdiagonal, L[i][j+1] at (i, j)). */

@@ -58,6 +58,8 @@ def lib():
         L.skltlt_factor.restype = i
         L.skltlt_pfaffian.argtypes = [i, vp, i, vp, vp, vp, vp, i, i, vp, sz, vp]
         L.skltlt_pfaffian.restype = i
+        L.skltlt_pfaffian_partial.argtypes = [i, vp, i, vp, vp, vp, vp, i, i, vp, sz, vp]
+        L.skltlt_pfaffian_partial.restype = i
         L.skltlt_batched_max_n.argtypes = []
         L.skltlt_batched_max_n.restype = i
         L.skltlt_batched_workspace_size.argtypes = [i, ctypes.POINTER(sz)]
@@ -146,6 +148,23 @@ def pfaffian(A, t, ipiv, log_abs_pf, sign, block_size: int = 0, precision: int =
                                work.numel(), _stream(stream))
     if st != SKLTLT_OK:
         raise SkltltError(st, "skltlt_pfaffian")
+    return st
+
+
+def pfaffian_partial(A, t, ipiv, log_abs_pf, sign, block_size: int = 0, precision: int = FP64,
+                     work=None, stream=None):
+    """skltlt_pfaffian_partial on device tensors: the Pfaffian by the
+    pairwise reduction; A is only read, t and ipiv receive the pairs' tau
+    and pivots."""
+    n = A.shape[0]
+    lda = _lda_of(A)
+    if work is None:
+        work = alloc_workspace(workspace_size(n, block_size, precision), A.device)
+    st = lib().skltlt_pfaffian_partial(n, _ptr(A), lda, _ptr(t), _ptr(ipiv), _ptr(log_abs_pf),
+                                       _ptr(sign), int(block_size), int(precision), _ptr(work),
+                                       work.numel(), _stream(stream))
+    if st != SKLTLT_OK:
+        raise SkltltError(st, "skltlt_pfaffian_partial")
     return st
 
 

@@ -68,6 +68,10 @@ hipError_t launch_panel(double *A, int lda, const double *W, int n, int k0, int 
                         double *t, int *ipiv, const FactorWs &ws, int want32,
                         const PanelShape &sh, hipStream_t s);
 
+// Pfaffian-only panel: pairs of columns, one pivot per pair (nb even).
+hipError_t launch_panel_pair(const double *W, int n, int k0, int nb, int b, double *t, int *ipiv,
+                             const FactorWs &ws, int want32, const PanelShape &sh, hipStream_t s);
+
 // Wn[i][j] = Wc[perm[i]][perm[j]] - (U V^T - V U^T)[i][j] for i != j >= cp.
 hipError_t launch_skr2k(const double *Wc, double *Wn, int n, int cp, int nq,
                         const FactorWs &ws, int precision, hipStream_t s);
@@ -130,6 +134,6 @@ int tm_begin(int cls, hipStream_t s);
 void tm_end(int idx, hipStream_t s, double flops);
 void panel_init_attrs();
 void finalize_init_attrs();
-int panel_max_groups(size_t lds_bytes);
+int panel_max_groups(size_t lds_bytes, bool pair);
 
 }  // namespace skl

@@ -141,8 +141,241 @@ __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); 
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// The pivot exchange between groups.  A slot is one 16-byte access.  Each
+// of its four dwords carries the step stamp (4 bits: a slot is rewritten
+// every second step, so the stale contents it can hold are one write old)
+// above 28 payload bits: the candidate value (64 bits), its row relative to
+// the panel base (24 bits, 0xffffff: none) and its register row (24 bits).
+// A reader accepts the slot when all four stamps match, so a read that mixes
+// two writes is never taken for a complete one.  Each slot has a 128-byte
+// L2 line of its own: slots that share a line make writers on different
+// XCDs contend for it (measured slower).
+struct SlotIO {
+    __amdgpu_buffer_rsrc_t srs;
+    int base;   // the panel's first trailing row
+    bool local; // every group on one XCD
+
+    __device__ __forceinline__ SlotIO(Slot *slots, int base_, bool local_)
+        : srs(__builtin_amdgcn_make_buffer_rsrc((void *)slots, (short)0,
+                                                (int)(kSlotBytes * 2 * kSlotsPerParity),
+                                                0x00020000)),
+          base(base_), local(local_)
+    {
+    }
+    __device__ __forceinline__ void publish(int q, unsigned stamp, double v, int idx,
+                                            int ph) const
+    {
+        const unsigned long long xb = (unsigned long long)__double_as_longlong(v);
+        const unsigned vhi = (unsigned)(xb >> 32), vlo = (unsigned)xb;
+        const unsigned ib = (idx == INT_MAX) ? 0xffffffu : (unsigned)(idx - base);
+        const unsigned st = (stamp & 0xfu) << 28;
+        u32x4 d;
+        d.x = st | (vhi >> 4);
+        d.y = st | ((vhi & 0xfu) << 24) | (vlo >> 8);
+        d.z = st | ((vlo & 0xffu) << 20) | (ib >> 4);
+        d.w = st | ((ib & 0xfu) << 24) | ((unsigned)ph & 0xffffffu);
+        if (local)
+            __builtin_amdgcn_raw_buffer_store_b128(d, srs, q * kSlotBytes, 0, 0);
+        else // device scope (sc1): visible to other XCDs without an L2 write-back
+            __builtin_amdgcn_raw_buffer_store_b128(d, srs, q * kSlotBytes, 0, 16);
+    }
+    __device__ __forceinline__ u32x4 load(int q) const
+    {
+        return __builtin_amdgcn_raw_buffer_load_b128(srs, q * kSlotBytes, 0, 16);
+    }
+    __device__ static __forceinline__ bool ready(u32x4 d, unsigned stamp)
+    {
+        const unsigned s4 = stamp & 0xfu;
+        return ((d.x >> 28) == s4) & ((d.y >> 28) == s4) & ((d.z >> 28) == s4) &
+               ((d.w >> 28) == s4);
+    }
+    // Folds a slot's candidate into (gv, gi, gph) in the pivot order.
+    __device__ __forceinline__ void fold(u32x4 d, double &gv, int &gi, int &gph) const
+    {
+        const unsigned vhi = ((d.x & 0x0fffffffu) << 4) | ((d.y >> 24) & 0xfu);
+        const unsigned vlo = ((d.y & 0x00ffffffu) << 8) | ((d.z >> 20) & 0xffu);
+        const unsigned ib = ((d.z & 0x000fffffu) << 4) | ((d.w >> 24) & 0xfu);
+        const double v2 = __longlong_as_double((long long)(((unsigned long long)vhi << 32) | vlo));
+        const int i2 = (ib == 0xffffffu) ? INT_MAX : base + (int)ib;
+        const bool wn = beats(v2, i2, gv, gi);
+        gv = wn ? v2 : gv;
+        gi = wn ? i2 : gi;
+        gph = wn ? (int)(d.w & 0x00ffffffu) : gph;
+    }
+};
+
 // bounded waits: a stuck peer never hangs the GPU (the result is poisoned)
 constexpr long kSpinLimit = 1L << 20;
+
+// LDS state of a group's pivot search.
+template <int NW>
+struct PivotLds {
+    double red_v[NW];
+    int red_i[NW], red_ph[NW];
+    double bc_tau;
+    int bc_p, bc_physp, bc_fail;
+    double hand_v; // wave 1 -> wave 0 handoff of polled candidates
+    int hand_i, hand_ph;
+    unsigned hand_flag;
+};
+
+// Reduces the per-wave candidates (waves without one hold v = 0,
+// idx = INT_MAX) in the pivot order; one thread.
+template <int NW>
+__device__ __forceinline__ void reduce_waves(const double *red_v, const int *red_i,
+                                             const int *red_ph, double &bv, int &bi, int &bph)
+{
+    double rv[NW];
+    int ri[NW], rph[NW];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        rv[q] = red_v[q];
+        ri[q] = red_i[q];
+        rph[q] = red_ph[q];
+    }
+    bv = rv[0];
+    bi = ri[0];
+    bph = rph[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) {
+        const bool wn = beats(rv[q], ri[q], bv, bi);
+        bv = wn ? rv[q] : bv;
+        bi = wn ? ri[q] : bi;
+        bph = wn ? rph[q] : bph;
+    }
+}
+
+// The step's pivot, broadcast through LDS; an index that does not name an
+// existing candidate row can only follow a failed wait and poisons the
+// result (tau = NaN) while keeping every later access in range.
+template <int NW>
+__device__ __forceinline__ void set_pivot(PivotLds<NW> &pl, double v, int idx, int ph, int r_cur,
+                                          int n, int G, int R, int base)
+{
+    if (idx < r_cur || idx >= n || ph < 0 || ph >= G * R || base + ph >= n) {
+        pl.bc_p = r_cur;
+        pl.bc_physp = 0;
+        pl.bc_fail = 1;
+    } else {
+        pl.bc_p = idx;
+        pl.bc_physp = ph;
+    }
+    pl.bc_tau = v;
+}
+
+// Group argmax of the candidates (cv, ci, cph) (lanes without one hold
+// v = 0, idx = INT_MAX) and, with several groups, the exchange through the
+// slots: each group publishes its candidate and polls all slots of this
+// parity, and every group reduces them to the same pivot.  Ends with a
+// barrier after which pl.bc_* hold the pivot.  The caller's mirror stores
+// (this wave's) are complete before the slot is published.
+template <int NT>
+__device__ __forceinline__ void find_pivot(PivotLds<NT / 64> &pl, const SlotIO &sio, bool multi,
+                                           int G, int w, int par, unsigned stamp, int r_cur, int n,
+                                           int R, double cv, int ci, int cph)
+{
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    wave_argmax(cv, ci, cph);
+    if (lane == 0) {
+        pl.red_v[wave] = cv;
+        pl.red_i[wave] = ci;
+        pl.red_ph[wave] = cph;
+    }
+    // this wave's mirror stores of the previous step must be complete
+    // before the group's slot is published
+    if (multi)
+        wait_vm();
+    __syncthreads();
+    if (tid == 0) {
+        double bv;
+        int bi, bph;
+        reduce_waves<NW>(pl.red_v, pl.red_i, pl.red_ph, bv, bi, bph);
+        if (multi)
+            sio.publish(par * kSlotsPerParity + w, stamp, bv, bi, bph);
+        else
+            set_pivot<NW>(pl, bv, bi, bph, r_cur, n, G, R, sio.base);
+    }
+
+    // several groups: poll all slots and reduce them identically in every
+    // group
+    if (multi) {
+        double gv = 0.0;
+        int gi = INT_MAX, gph = 0;
+        for (int q = tid; q < G; q += NT) {
+            u32x4 d;
+            long spins = 0;
+            for (;;) {
+                // compiler-only fence: the slot load is an ordinary
+                // intrinsic and would otherwise be hoisted out of the spin
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                d = sio.load(par * kSlotsPerParity + q);
+                if (SlotIO::ready(d, stamp))
+                    break;
+                if (pl.bc_fail || ++spins > kSpinLimit) {
+                    pl.bc_fail = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            sio.fold(d, gv, gi, gph);
+        }
+        if (G <= 128) {
+            // every candidate is in waves 0 and 1: wave 1 hands its result
+            // to wave 0 through LDS (no barrier), wave 0 broadcasts the pivot
+            if (wave == 1 && G > 64) {
+                wave_argmax(gv, gi, gph);
+                if (lane == 0) {
+                    pl.hand_v = gv;
+                    pl.hand_i = gi;
+                    pl.hand_ph = gph;
+                    __hip_atomic_store(&pl.hand_flag, stamp, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            } else if (wave == 0) {
+                wave_argmax(gv, gi, gph);
+                if (lane == 0) {
+                    if (G > 64) {
+                        long hs = 0;
+                        while (__hip_atomic_load(&pl.hand_flag, __ATOMIC_ACQUIRE,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP) != stamp) {
+                            if (++hs > kSpinLimit) {
+                                pl.bc_fail = 1;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                        const double hv2 = pl.hand_v;
+                        const int hi2 = pl.hand_i, hph2 = pl.hand_ph;
+                        const bool wn = beats(hv2, hi2, gv, gi);
+                        gv = wn ? hv2 : gv;
+                        gi = wn ? hi2 : gi;
+                        gph = wn ? hph2 : gph;
+                    }
+                    set_pivot<NW>(pl, gv, gi, gph, r_cur, n, G, R, sio.base);
+                }
+            }
+        } else {
+            if (wave * 64 < G)
+                wave_argmax(gv, gi, gph);
+            __syncthreads(); // red_* of the group argmax were consumed by thread 0
+            if (lane == 0) {
+                pl.red_v[wave] = gv;
+                pl.red_i[wave] = gi;
+                pl.red_ph[wave] = gph;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double bv;
+                int bi, bph;
+                reduce_waves<NW>(pl.red_v, pl.red_i, pl.red_ph, bv, bi, bph);
+                set_pivot<NW>(pl, bv, bi, bph, r_cur, n, G, R, sio.base);
+            }
+        }
+    }
+    __syncthreads();
+}
+
 
 template <int NT, int TPR, int kNS>
 __global__ __launch_bounds__(NT) void panel_kernel(
@@ -167,18 +400,11 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     __shared__ double tl[kMaxBlock];
     __shared__ int pl[kMaxBlock];
     __shared__ int posl[R];
-    __shared__ double red_v[NW];
-    __shared__ int red_i[NW], red_ph[NW];
-    __shared__ double bc_tau;
-    __shared__ int bc_p, bc_physp, bc_fail;
-    __shared__ double hand_v; // wave 1 -> wave 0 handoff of polled candidates
-    __shared__ int hand_i, hand_ph;
-    __shared__ unsigned hand_flag;
+    __shared__ PivotLds<NW> pv;
 
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
     // With one_xcd the grid holds 8 workgroups per panel group and only those
     // with an id divisible by 8 work: workgroup ids are dealt round-robin to
     // the 8 XCDs, so all working groups share one XCD, which shortens the
@@ -239,98 +465,15 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     }
     ycol = __shfl(ycol, lane & ~(TPR - 1), 64);
     if (tid == 0) {
-        bc_fail = 0;
-        hand_flag = 0u;
+        pv.bc_fail = 0;
+        pv.hand_flag = 0u;
     }
     __syncthreads();
-
-    // Broadcast the step's pivot through LDS; an index that does not name an
-    // existing candidate row can only follow a failed wait and poisons the
-    // result (tau = NaN) while keeping every later access in range.
-    int r_cur = 0;
-    auto set_pivot = [&](double v, int idx, int ph) {
-        if (idx < r_cur || idx >= n || ph < 0 || ph >= G * R || base + ph >= n) {
-            bc_p = r_cur;
-            bc_physp = 0;
-            bc_fail = 1;
-        } else {
-            bc_p = idx;
-            bc_physp = ph;
-        }
-        bc_tau = v;
-    };
-    // A slot is one 16-byte access.  Each of its four dwords carries the
-    // step stamp (4 bits: a slot is rewritten every second step, so the
-    // stale contents it can hold are one write old) above 28 payload bits:
-    // the candidate value (64 bits), its row relative to the panel base
-    // (24 bits, 0xffffff: none) and its register row (24 bits).  A reader
-    // accepts the slot when all four stamps match, so a read that mixes two
-    // writes is never taken for a complete one.
-    // Each slot has a 128-byte L2 line of its own: slots that share a line
-    // make writers on different XCDs contend for it (measured slower).
-    const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)slots, (short)0, (int)(kSlotBytes * 2 * kSlotsPerParity), 0x00020000);
-    auto publish_slot = [&](int q, unsigned stamp, double v, int idx, int ph) {
-        const unsigned long long xb = (unsigned long long)__double_as_longlong(v);
-        const unsigned vhi = (unsigned)(xb >> 32), vlo = (unsigned)xb;
-        const unsigned ib = (idx == INT_MAX) ? 0xffffffu : (unsigned)(idx - base);
-        const unsigned st = (stamp & 0xfu) << 28;
-        u32x4 d;
-        d.x = st | (vhi >> 4);
-        d.y = st | ((vhi & 0xfu) << 24) | (vlo >> 8);
-        d.z = st | ((vlo & 0xffu) << 20) | (ib >> 4);
-        d.w = st | ((ib & 0xfu) << 24) | ((unsigned)ph & 0xffffffu);
-        if (local)
-            __builtin_amdgcn_raw_buffer_store_b128(d, srs, q * kSlotBytes, 0, 0);
-        else // device scope (sc1): visible to other XCDs without an L2 write-back
-            __builtin_amdgcn_raw_buffer_store_b128(d, srs, q * kSlotBytes, 0, 16);
-    };
-    auto load_slot = [&](int q) {
-        return __builtin_amdgcn_raw_buffer_load_b128(srs, q * kSlotBytes, 0, 16);
-    };
-    auto slot_ready = [](u32x4 d, unsigned stamp) {
-        const unsigned s4 = stamp & 0xfu;
-        return ((d.x >> 28) == s4) & ((d.y >> 28) == s4) & ((d.z >> 28) == s4) &
-               ((d.w >> 28) == s4);
-    };
-    auto fold_slot = [&](u32x4 d, double &gv, int &gi, int &gph) {
-        const unsigned vhi = ((d.x & 0x0fffffffu) << 4) | ((d.y >> 24) & 0xfu);
-        const unsigned vlo = ((d.y & 0x00ffffffu) << 8) | ((d.z >> 20) & 0xffu);
-        const unsigned ib = ((d.z & 0x000fffffu) << 4) | ((d.w >> 24) & 0xfu);
-        const double v2 = __longlong_as_double((long long)(((unsigned long long)vhi << 32) | vlo));
-        const int i2 = (ib == 0xffffffu) ? INT_MAX : base + (int)ib;
-        const bool wn = beats(v2, i2, gv, gi);
-        gv = wn ? v2 : gv;
-        gi = wn ? i2 : gi;
-        gph = wn ? (int)(d.w & 0x00ffffffu) : gph;
-    };
-    // thread 0: reduce the per-wave candidates in red_* (waves without a
-    // candidate hold v = 0, idx = INT_MAX)
-    auto reduce_red = [&](double &bv, int &bi, int &bph) {
-        double rv[NW];
-        int ri[NW], rph[NW];
-#pragma unroll
-        for (int q = 0; q < NW; ++q) {
-            rv[q] = red_v[q];
-            ri[q] = red_i[q];
-            rph[q] = red_ph[q];
-        }
-        bv = rv[0];
-        bi = ri[0];
-        bph = rph[0];
-#pragma unroll
-        for (int q = 1; q < NW; ++q) {
-            const bool wn = beats(rv[q], ri[q], bv, bi);
-            bv = wn ? rv[q] : bv;
-            bi = wn ? ri[q] : bi;
-            bph = wn ? rph[q] : bph;
-        }
-    };
+    const SlotIO sio(slots, base, local);
 
     for (int j = 0; j < nb; ++j) {
         const int c = k0 + j;
         const int r = c + 1;
-        r_cur = r;
         const int par = c & 1;
         const unsigned stamp = (unsigned)(c + 1);
 
@@ -387,121 +530,21 @@ __global__ __launch_bounds__(NT) void panel_kernel(
             s += __shfl_xor(s, off, 64);
         const double xv = ycol - s;
 
-        // 3. group argmax: largest |x|, smallest row index on ties (each
-        //    wave, then thread 0 over the waves).
-        double cv = 0.0;
-        int ci = INT_MAX, cph = 0;
-        if (cand && sub == 0) {
-            cv = xv;
-            ci = pos;
-            cph = phys;
-        }
-        wave_argmax(cv, ci, cph);
-        if (lane == 0) {
-            red_v[wave] = cv;
-            red_i[wave] = ci;
-            red_ph[wave] = cph;
-        }
-        // this wave's mirror stores of the previous step must be complete
-        // before the group's slot is published
-        if (multi)
-            wait_vm();
-        __syncthreads();
-        if (tid == 0) {
-            if (multi) {
-                double bv;
-                int bi, bph;
-                reduce_red(bv, bi, bph);
-                publish_slot(par * kSlotsPerParity + w, stamp, bv, bi, bph);
-            } else {
-                double bv;
-                int bi, bph;
-                reduce_red(bv, bi, bph);
-                set_pivot(bv, bi, bph);
+        // 3-4. group argmax, then (several groups) the exchange of the
+        //      groups' candidates: every group arrives at the same pivot.
+        {
+            double cv = 0.0;
+            int ci = INT_MAX, cph = 0;
+            if (cand && sub == 0) {
+                cv = xv;
+                ci = pos;
+                cph = phys;
             }
+            find_pivot<NT>(pv, sio, multi, G, w, par, stamp, r, n, R, cv, ci, cph);
         }
-
-        // 4. several groups: poll all slots and reduce them identically in
-        //    every group.
-        if (multi) {
-            double gv = 0.0;
-            int gi = INT_MAX, gph = 0;
-            for (int q = tid; q < G; q += NT) {
-                u32x4 d;
-                long spins = 0;
-                for (;;) {
-                    // compiler-only fence: the slot load is an ordinary
-                    // intrinsic and would otherwise be hoisted out of the spin
-                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                    d = load_slot(par * kSlotsPerParity + q);
-                    if (slot_ready(d, stamp))
-                        break;
-                    if (bc_fail || ++spins > kSpinLimit) {
-                        bc_fail = 1;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                fold_slot(d, gv, gi, gph);
-            }
-            if (G <= 128) {
-                // every candidate is in waves 0 and 1: wave 1 hands its
-                // result to wave 0 through LDS (no barrier), wave 0
-                // broadcasts the pivot
-                if (wave == 1 && G > 64) {
-                    wave_argmax(gv, gi, gph);
-                    if (lane == 0) {
-                        hand_v = gv;
-                        hand_i = gi;
-                        hand_ph = gph;
-                        __hip_atomic_store(&hand_flag, stamp, __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                    }
-                } else if (wave == 0) {
-                    wave_argmax(gv, gi, gph);
-                    if (lane == 0) {
-                        if (G > 64) {
-                            long hs = 0;
-                            while (__hip_atomic_load(&hand_flag, __ATOMIC_ACQUIRE,
-                                                     __HIP_MEMORY_SCOPE_WORKGROUP) != stamp) {
-                                if (++hs > kSpinLimit) {
-                                    bc_fail = 1;
-                                    break;
-                                }
-                                __builtin_amdgcn_s_sleep(1);
-                            }
-                            const double hv2 = hand_v;
-                            const int hi2 = hand_i, hph2 = hand_ph;
-                            const bool wn = beats(hv2, hi2, gv, gi);
-                            gv = wn ? hv2 : gv;
-                            gi = wn ? hi2 : gi;
-                            gph = wn ? hph2 : gph;
-                        }
-                        set_pivot(gv, gi, gph);
-                    }
-                }
-            } else {
-                if (wave * 64 < G)
-                    wave_argmax(gv, gi, gph);
-                __syncthreads(); // red_* of step 3 were consumed by thread 0
-                if (lane == 0) {
-                    red_v[wave] = gv;
-                    red_i[wave] = gi;
-                    red_ph[wave] = gph;
-                }
-                __syncthreads();
-                if (tid == 0) {
-                    double bv;
-                    int bi, bph;
-                    reduce_red(bv, bi, bph);
-                    set_pivot(bv, bi, bph);
-                }
-            }
-        }
-        __syncthreads();
-        const int p = bc_p;
-        const double tau = bc_fail ? __longlong_as_double(0x7ff8000000000000ll) : bc_tau;
-        const int physp = bc_physp;
+        const int p = pv.bc_p;
+        const double tau = pv.bc_fail ? __longlong_as_double(0x7ff8000000000000ll) : pv.bc_tau;
+        const int physp = pv.bc_physp;
 
         // 5a. the pivot row of L (row p before the exchange): it is the
         //     previous row for the next step's h.
@@ -641,6 +684,340 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     }
 }
 
+// Pfaffian-only panel (Wimmer's reduction: Sec. 3.5.2, Notes, and the
+// accumulated rank-2k form of Sec. 3.6.5, Note).  Columns come in pairs
+// (c, c+1), c even; only c is pivoted.  With M the panel's accumulated
+// columns, M[:, 2i] = l_i (the pair's Gauss vector) and M[:, 2i+1] = c_i
+// (its second column), the trailing matrix as of column step c is
+// Y + sum_i (l_i c_i^T - c_i l_i^T) = Y - M h-products, so a column is
+// x = Y[:, label] - M h with h[2i] = -c_i[label], h[2i+1] = l_i[label].
+// Per pair:
+//   1. x_c = Y[:, c] - M h_c over the earlier pairs; argmax over rows > c
+//      and the slot exchange (as in the full panel) give the pivot p;
+//   2. relabel r = c+1 <-> p; load the pivot row's M entries, the row that
+//      now holds label c+2 (its M entries and two W entries), and the W
+//      columns of labels r and c+2 (one round trip for all of them);
+//   3. l_i = x_c / tau for rows > r; the pair's second column
+//      x_r = Y[:, r] - M h_r over the earlier pairs only (the pair's own
+//      update leaves it unchanged), c_i = x_r for rows > r;
+//   4. h for column c+2 is formed by every group from the fetched row: its
+//      l_i and c_i entries are recomputed there with the same formulas
+//      (two dot products over the group), so no third exchange is needed.
+// Two device round trips per pair instead of four for the two columns of
+// the full panel.  Nothing is written to A; t and ipiv receive the pairs'
+// tau and pivots (0 and no exchange at the odd positions); the skr2k
+// operands are U = [c_i], V = [l_i].
+template <int NT, int TPR, int kNS>
+__global__ __launch_bounds__(NT) void panel_pair_kernel(
+    const double *__restrict__ W, int ldw, int n, int k0, int nb, double *__restrict__ t,
+    int *__restrict__ ipiv, int *__restrict__ perm, double *__restrict__ mirror, int ldm,
+    double *__restrict__ uv, float *__restrict__ uv32, int want32, Slot *__restrict__ slots,
+    int G, int one_xcd)
+{
+    constexpr int R = NT / TPR;
+    constexpr int NW = NT / 64;
+    constexpr int kRing = 4; // (8 spills registers here)
+    constexpr int kNSR = ((kNS + kRing - 1) / kRing) * kRing;
+    constexpr int NA = kNSR * TPR; // columns addressable through the ring
+    static_assert(NA <= NT, "one thread per h entry");
+    extern __shared__ double stage[]; // R x 34, epilogue only
+
+    __shared__ double hv[NA]; // h of the pair's first column
+    __shared__ double ho[NA]; // h of its second column
+    __shared__ double tl[kMaxBlock / 2];
+    __shared__ int pl[kMaxBlock / 2];
+    __shared__ int wphys[kMaxBlock]; // register row of each label base .. base+nb-1
+    __shared__ int posl[R];
+    __shared__ double dred[2][NW];
+    __shared__ PivotLds<NW> pv;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int w = blockIdx.x;
+    if (one_xcd) {
+        if (w & 7)
+            return;
+        w >>= 3;
+    }
+    const int base = k0 + 1;
+    const int lr = tid / TPR;
+    const int sub = tid - lr * TPR;
+    const int phys = w * R + lr;
+    const int orow = base + phys;
+    const bool multi = (G > 1);
+    const bool local = (one_xcd != 0);
+    int pos = orow;
+    const bool exists = (orow < n);
+
+    double Lreg[kNS];
+    double Lnew[kRing];
+#pragma unroll
+    for (int q = 0; q < kNS; ++q)
+        Lreg[q] = 0.0;
+#pragma unroll
+    for (int i = 0; i < kRing; ++i)
+        Lnew[i] = 0.0;
+    auto flush_ring = [&](int g) {
+#pragma unroll
+        for (int q = 0; q < kNS; ++q)
+            Lreg[q] = (q / kRing == g) ? Lnew[q % kRing] : Lreg[q];
+#pragma unroll
+        for (int i = 0; i < kRing; ++i)
+            Lnew[i] = 0.0;
+    };
+    int grc = 0; // ring group held in Lnew (uniform)
+    // column a of M for this row (thread a % TPR keeps it)
+    auto insert = [&](int a, double v, bool mine) {
+        const int g = (a / TPR) / kRing;
+        if (g != grc) {
+            flush_ring(grc);
+            grc = g;
+        }
+        if (mine && sub == a % TPR) {
+            const int slot = (a / TPR) % kRing;
+#pragma unroll
+            for (int i = 0; i < kRing; ++i)
+                Lnew[i] = (i == slot) ? v : Lnew[i];
+        }
+    };
+    // x = y - sum_a M[row][a] h[a] over the filled columns
+    auto gemv = [&](const double *h, double y) {
+        constexpr int kHB = 8; // (16 spills registers here)
+        double sacc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int qb = 0; qb < kNS; qb += kHB) {
+            if (qb < grc * kRing) {
+                double hh[kHB];
+#pragma unroll
+                for (int i = 0; i < kHB; ++i)
+                    hh[i] = (qb + i < kNS) ? h[sub + TPR * (qb + i)] : 0.0;
+#pragma unroll
+                for (int i = 0; i < kHB; ++i)
+                    if (qb + i < kNS)
+                        sacc[i & 3] += Lreg[qb + i] * hh[i];
+            }
+        }
+        {
+            double hh[kRing];
+#pragma unroll
+            for (int i = 0; i < kRing; ++i)
+                hh[i] = h[sub + TPR * (grc * kRing + i)];
+#pragma unroll
+            for (int i = 0; i < kRing; ++i)
+                sacc[i & 3] += Lnew[i] * hh[i];
+        }
+        double sm = (sacc[0] + sacc[1]) + (sacc[2] + sacc[3]);
+#pragma unroll
+        for (int off = TPR >> 1; off >= 1; off >>= 1)
+            sm += __shfl_xor(sm, off, 64);
+        return y - sm;
+    };
+
+    double ycol = 0.0;
+    for (int a = tid; a < NA; a += NT) {
+        hv[a] = 0.0;
+        ho[a] = 0.0;
+    }
+    for (int q = tid; q < nb; q += NT)
+        wphys[q] = q;
+    if (exists && sub == 0)
+        ycol = W[(size_t)k0 * ldw + orow];
+    ycol = __shfl(ycol, lane & ~(TPR - 1), 64);
+    if (tid == 0) {
+        pv.bc_fail = 0;
+        pv.hand_flag = 0u;
+    }
+    __syncthreads();
+    const SlotIO sio(slots, base, local);
+    const double qnan = __longlong_as_double(0x7ff8000000000000ll);
+
+    const int npair = nb / 2;
+    for (int i = 0; i < npair; ++i) {
+        const int c = k0 + 2 * i; // the pair's pivoted column
+        const int r = c + 1;
+        const int pr = (c >> 1) & 1;
+        const unsigned stamp = (unsigned)((c >> 1) + 1);
+        // window labels: r = base + 2i, c+2 = base + 2i + 1, c = base + 2i - 1
+        const int physR0 = wphys[2 * i];
+        const int physE0 = (2 * i + 1 < nb) ? wphys[2 * i + 1] : 0;
+        const int origC = (i == 0) ? k0 : base + wphys[2 * i - 1];
+
+        // 1. x_c and the pivot
+        const double xv = gemv(hv, ycol);
+        // one group: its own mirror stores must be complete before the
+        // barrier in the pivot search (several groups wait there anyway)
+        if (!multi)
+            wait_vm();
+        {
+            double cv = 0.0;
+            int ci = INT_MAX, cph = 0;
+            if (exists && pos >= r && sub == 0) {
+                cv = xv;
+                ci = pos;
+                cph = phys;
+            }
+            find_pivot<NT>(pv, sio, multi, G, w, pr, stamp, r, n, R, cv, ci, cph);
+        }
+        const int p = pv.bc_p;
+        const double tau = pv.bc_fail ? qnan : pv.bc_tau;
+        const int physp = pv.bc_physp;
+
+        // 2. relabel, then one round of loads
+        if (exists) {
+            if (pos == r)
+                pos = p;
+            else if (pos == p)
+                pos = r;
+        }
+        const bool nxt = (i + 1 < npair); // column c+2 belongs to this panel
+        const int physE = (p == c + 2) ? physR0 : physE0; // row holding label c+2
+        double yo = 0.0, ye = 0.0;
+        if (exists && sub == 0 && pos > r)
+            yo = W[(size_t)(base + physp) * ldw + orow];
+        if (nxt && exists && sub == 0 && pos > c + 2)
+            ye = W[(size_t)(base + physE) * ldw + orow];
+        const int a = tid;
+        const bool ha = (a < 2 * i);
+        double mp1 = 0.0, me0 = 0.0, me1 = 0.0, wsc = 0.0;
+        if (ha) {
+            mp1 = ld_dev(&mirror[(size_t)physp * ldm + (a ^ 1)]);
+            if (nxt) {
+                me0 = ld_dev(&mirror[(size_t)physE * ldm + a]);
+                me1 = ld_dev(&mirror[(size_t)physE * ldm + (a ^ 1)]);
+            }
+        }
+        // entries (label c+2, label r) and (label c+2, label c) of Y
+        if (nxt && a == 2 * i)
+            wsc = W[(size_t)(base + physp) * ldw + base + physE];
+        if (nxt && a == 2 * i + 1)
+            wsc = W[(size_t)origC * ldw + base + physE];
+
+        // 3a. l_i for the rows below r
+        const bool below = exists && pos > r;
+        const double lval = below ? ((tau != 0.0) ? xv / tau : 0.0) : 0.0;
+        insert(2 * i, lval, below);
+        if (below && sub == (2 * i) % TPR)
+            st_xcd(&mirror[(size_t)phys * ldm + 2 * i], lval, local);
+        // h of the second column (pivot row entries) and the two dot
+        // products of the label-(c+2) row with h_c and h_r
+        const double hoa = ha ? ((a & 1) ? mp1 : -mp1) : 0.0;
+        const double hea = ha ? ((a & 1) ? me1 : -me1) : 0.0;
+        double dk = 0.0, dob = 0.0;
+        if (a < NA) {
+            ho[a] = hoa;
+            if (ha) {
+                dk = me0 * hv[a];
+                dob = me0 * hoa;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            dk += __shfl_xor(dk, off, 64);
+            dob += __shfl_xor(dob, off, 64);
+        }
+        if (lane == 0) {
+            dred[0][wave] = dk;
+            dred[1][wave] = dob;
+        }
+        __syncthreads();
+
+        // 3b. the pair's second column and c_i
+        ycol = __shfl(yo, lane & ~(TPR - 1), 64);
+        const double xo = gemv(ho, ycol);
+        insert(2 * i + 1, below ? xo : 0.0, below);
+        if (below && sub == (2 * i + 1) % TPR)
+            st_xcd(&mirror[(size_t)phys * ldm + 2 * i + 1], xo, local);
+
+        // 4. h of column c+2: earlier pairs from the fetched row; this
+        //    pair's c_i and l_i at label c+2 recomputed from the same data
+        if (nxt && a <= 2 * i + 1) {
+            double hn = hea;
+            if (a >= 2 * i) {
+                double sk = 0.0, so = 0.0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    sk += dred[0][q];
+                    so += dred[1][q];
+                }
+                if (a == 2 * i) // -c_i[c+2]
+                    hn = -(wsc - so);
+                else { // l_i[c+2]
+                    const double xk = wsc - sk;
+                    hn = (tau != 0.0) ? xk / tau : 0.0;
+                }
+            }
+            hv[a] = hn;
+        }
+        ycol = __shfl(ye, lane & ~(TPR - 1), 64);
+        if (tid == 0) {
+            tl[i] = tau;
+            pl[i] = p;
+            wphys[2 * i] = physp;
+            if (p - base < nb && p != r)
+                wphys[p - base] = physR0;
+        }
+        __syncthreads();
+    }
+    flush_ring(grc);
+
+    // ---- panel end: tau and pivots of the pairs, the permutation, and the
+    //      skr2k operands U_q = c_q, V_q = l_q for the rows >= cp
+    if (w == 0) {
+        for (int q = tid; q < npair; q += NT) {
+            const int c = k0 + 2 * q;
+            t[c] = tl[q];
+            ipiv[c + 1] = pl[q];
+            if (c + 1 < n - 1)
+                t[c + 1] = 0.0;
+            if (c + 2 < n)
+                ipiv[c + 2] = c + 2;
+        }
+    }
+    const int cp = k0 + nb;
+    if (sub == 0) {
+        posl[lr] = exists ? pos : -1;
+        if (exists)
+            perm[pos] = orow;
+    }
+    if (cp < n - 1) {
+        const int nq = npair;
+        for (int c0 = 0; c0 < nb; c0 += 32) {
+            if (exists) {
+#pragma unroll
+                for (int q = 0; q < kNS; ++q) {
+                    const int aa = sub + TPR * q;
+                    if (aa >= c0 && aa < c0 + 32)
+                        stage[(size_t)lr * 34 + (aa - c0)] = (aa < nb) ? Lreg[q] : 0.0;
+                }
+            }
+            __syncthreads();
+            const int qlo = c0 / 2, qhi = min(nq, qlo + 16);
+            for (int e = tid; e < R * (qhi - qlo); e += NT) {
+                const int rr = e % R;
+                const int qq = qlo + e / R;
+                const int row = posl[rr];
+                if (row >= cp && row < n) {
+                    const double *srow = stage + (size_t)rr * 34;
+                    const double uq = srow[2 * qq + 1 - c0]; // c_q
+                    const double vq = srow[2 * qq - c0];     // l_q
+                    uv[(size_t)qq * n + row] = uq;
+                    uv[(size_t)(nq + qq) * n + row] = vq;
+                    uv[(size_t)(2 * nq + qq) * n + row] = -vq;
+                    uv[(size_t)(3 * nq + qq) * n + row] = uq;
+                    if (want32) {
+                        uv32[(size_t)qq * n + row] = (float)uq;
+                        uv32[(size_t)(nq + qq) * n + row] = (float)vq;
+                        uv32[(size_t)(2 * nq + qq) * n + row] = -(float)vq;
+                        uv32[(size_t)(3 * nq + qq) * n + row] = (float)uq;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // Panel shapes: 512 threads per group, TPR threads per row, kNS register
 // slots per thread holding b + 1 columns; R = 512 / TPR rows per group.
 //   b <= 64:  TPR 1, 65 slots, 512 rows (n = 16384 needs 32 groups: one XCD)
@@ -710,8 +1087,47 @@ hipError_t launch_panel(double *A, int lda, const double *W, int n, int k0, int 
     }
 }
 
+template <int TPR, int NS>
+static hipError_t launch_pair_t(const double *W, int n, int k0, int nb, double *t, int *ipiv,
+                                const FactorWs &ws, int want32, const PanelShape &sh,
+                                hipStream_t s)
+{
+    int ldw = ws.ldw;
+    int *perm = ws.perm;
+    double *mirror = ws.mirror;
+    int ldm = ws.ldm;
+    double *uv = ws.uv;
+    float *uv32 = ws.uv32;
+    Slot *slots = ws.slots;
+    int G = sh.G;
+    int one_xcd = (G > 1 && G <= kXcdCUs) ? 1 : 0;
+    void *args[] = {&W, &ldw, &n, &k0, &nb, &t, &ipiv, &perm, &mirror, &ldm,
+                    &uv, &uv32, &want32, &slots, &G, &one_xcd};
+    const void *fn = (const void *)panel_pair_kernel<kNT, TPR, NS>;
+    if (G == 1)
+        return hipLaunchKernel(fn, dim3(1), dim3(kNT), args, (unsigned)sh.lds, s);
+    const int grid = one_xcd ? 8 * G : G;
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kNT), args, (unsigned)sh.lds, s);
+}
+
+hipError_t launch_panel_pair(const double *W, int n, int k0, int nb, int b, double *t, int *ipiv,
+                             const FactorWs &ws, int want32, const PanelShape &sh, hipStream_t s)
+{
+    switch (shape_id(b)) {
+    case 0: return launch_pair_t<1, 64>(W, n, k0, nb, t, ipiv, ws, want32, sh, s);
+    case 1: return launch_pair_t<2, 64>(W, n, k0, nb, t, ipiv, ws, want32, sh, s);
+    default: return launch_pair_t<4, 64>(W, n, k0, nb, t, ipiv, ws, want32, sh, s);
+    }
+}
+
 void panel_init_attrs()
 {
+    (void)hipFuncSetAttribute((const void *)panel_pair_kernel<kNT, 1, 64>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)panel_pair_kernel<kNT, 2, 64>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)panel_pair_kernel<kNT, 4, 64>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipFuncSetAttribute((const void *)panel_kernel<kNT, 1, 65>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipFuncSetAttribute((const void *)panel_kernel<kNT, 2, 65>,
@@ -720,16 +1136,20 @@ void panel_init_attrs()
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
-int panel_max_groups(size_t lds_bytes)
+int panel_max_groups(size_t lds_bytes, bool pair)
 {
     static int cached_cus = 0;
     if (!cached_cus)
         cached_cus = device_cu_count();
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
-                                                     (const void *)panel_kernel<kNT, 2, 65>, kNT,
-                                                     lds_bytes) != hipSuccess)
+    int per_cu = 0, per_cu4 = 0;
+    const void *f2 = pair ? (const void *)panel_pair_kernel<kNT, 2, 64>
+                          : (const void *)panel_kernel<kNT, 2, 65>;
+    const void *f4 = pair ? (const void *)panel_pair_kernel<kNT, 4, 64>
+                          : (const void *)panel_kernel<kNT, 4, 65>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f2, kNT, lds_bytes) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu4, f4, kNT, lds_bytes) != hipSuccess)
         return 0;
+    per_cu = per_cu < per_cu4 ? per_cu : per_cu4;
     if (per_cu < 1)
         per_cu = 1;
     long g = (long)per_cu * cached_cus;

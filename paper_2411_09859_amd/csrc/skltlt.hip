@@ -191,7 +191,7 @@ static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int bloc
     const int want32 = (precision == SKLTLT_FP32_UPDATE);
     // panel geometry: as many groups as the device keeps resident
     PanelShape probe = panel_shape(n, 0, b, kMaxPanelGroups);
-    int maxg = panel_max_groups(probe.lds);
+    int maxg = panel_max_groups(probe.lds, false);
     if (maxg <= 0)
         return device_error(hipErrorInvalidValue, "panel occupancy query");
 
@@ -246,6 +246,84 @@ extern "C" int skltlt_pfaffian(int n, double *A, int lda, double *t, int *ipiv,
     int st = factor_impl(n, A, lda, t, ipiv, block_size, precision, work, work_bytes, s);
     if (st != SKLTLT_OK)
         return st;
+    const int ti = tm_begin(SKLTLT_K_PFAFFIAN, s);
+    hipError_t e = launch_pfaffian(n, t, ipiv, log_abs_pf, sign, s);
+    if (e != hipSuccess)
+        return device_error(e, "pfaffian launch");
+    tm_end(ti, s, 0.0);
+    return SKLTLT_OK;
+}
+
+extern "C" int skltlt_pfaffian_partial(int n, const double *A, int lda, double *t, int *ipiv,
+                                       double *log_abs_pf, int *sign, int block_size,
+                                       int precision, void *work, size_t work_bytes, void *stream)
+{
+    if (n < 0 || lda < (n > 1 ? n : 1) || block_size < 0 || !log_abs_pf || !sign)
+        return SKLTLT_EINVAL;
+    if (precision != SKLTLT_FP64 && precision != SKLTLT_FP32_UPDATE)
+        return SKLTLT_EINVAL;
+    if (n >= 1 && (!A || !ipiv))
+        return SKLTLT_EINVAL;
+    if (n >= 2 && !t)
+        return SKLTLT_EINVAL;
+    const int b0 = resolve_block(n, block_size);
+    int st = check_supported(n, b0);
+    if (st != SKLTLT_OK)
+        return st;
+    const int b = (b0 >= 2) ? (b0 & ~1) : 2; // pairs of columns
+    hipStream_t s = (hipStream_t)stream;
+    if (n >= 1) {
+        const size_t need = factor_ws_layout(n, b0, nullptr, nullptr);
+        if (!work || work_bytes < need || ((uintptr_t)work % kAlign) != 0)
+            return SKLTLT_EINVAL;
+    }
+    init_device_attrs();
+    FactorWs ws{};
+    if (n >= 1)
+        factor_ws_layout(n, b0, &ws, (char *)work);
+    if (n >= 1) {
+        const int ti = tm_begin(SKLTLT_K_OTHER, s);
+        hipError_t e = launch_set_int(ipiv, 0, s);
+        if (e != hipSuccess)
+            return device_error(e, "set ipiv[0]");
+        if (n > 1 && (e = launch_fill_zero(ws.slots, (size_t)kSlotBytes * 2 * kSlotsPerParity, s)) !=
+                         hipSuccess)
+            return device_error(e, "clear slots");
+        if (n > 1 && (e = launch_init_full(A, lda, n, ws.W[0], ws.ldw, s)) != hipSuccess)
+            return device_error(e, "full copy");
+        tm_end(ti, s, 0.0);
+    }
+    if (n > 1) {
+        const int want32 = (precision == SKLTLT_FP32_UPDATE);
+        PanelShape probe = panel_shape(n, 0, b, kMaxPanelGroups);
+        int maxg = panel_max_groups(probe.lds, true);
+        if (maxg <= 0)
+            return device_error(hipErrorInvalidValue, "panel occupancy query");
+        int cur = 0;
+        for (int k0 = 0; k0 + 1 < n; k0 += b) {
+            const int pairs_left = (n - k0) / 2;
+            const int nb = (b < 2 * pairs_left) ? b : 2 * pairs_left;
+            PanelShape sh = panel_shape(n, k0, b, maxg);
+            if (sh.lds > kLdsCap || sh.G > maxg)
+                return SKLTLT_ENOTSUP;
+            int ti = tm_begin(SKLTLT_K_PANEL, s);
+            hipError_t e = launch_panel_pair(ws.W[cur], n, k0, nb, b, t, ipiv, ws, want32, sh, s);
+            if (e != hipSuccess)
+                return device_error(e, "pair panel launch");
+            tm_end(ti, s, 0.0);
+            const int cp = k0 + nb;
+            if (cp < n - 1) {
+                const int nq = nb / 2;
+                const double m = (double)(n - cp);
+                ti = tm_begin(SKLTLT_K_SKR2K, s);
+                if ((e = launch_skr2k(ws.W[cur], ws.W[cur ^ 1], n, cp, nq, ws, precision, s)) !=
+                    hipSuccess)
+                    return device_error(e, "skr2k launch");
+                cur ^= 1;
+                tm_end(ti, s, m * (m - 1.0) * 0.5 * 2.0 * (2.0 * nq));
+            }
+        }
+    }
     const int ti = tm_begin(SKLTLT_K_PFAFFIAN, s);
     hipError_t e = launch_pfaffian(n, t, ipiv, log_abs_pf, sign, s);
     if (e != hipSuccess)
