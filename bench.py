@@ -238,6 +238,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--solve-steps", type=int, default=3,
                     help="timed solves with the factors (0: skip)")
+    ap.add_argument("--partial-steps", type=int, default=2,
+                    help="timed Pfaffian-only (partial) reductions (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -338,6 +340,32 @@ def main():
                  "backward_error": (torch.linalg.norm(r) / (nA * torch.linalg.norm(x))).item()}
         del low, r
         log(f"[bench] solve {solve}")
+
+    # Pfaffian only by the pairwise (partial) reduction of the same matrix
+    partial = None
+    if args.partial_steps > 0:
+        tp = torch.zeros_like(t)
+        ipp = torch.zeros_like(ipiv)
+        lap = torch.zeros_like(la)
+        sgp = torch.zeros_like(sg)
+        binding.pfaffian_partial(A0, tp, ipp, lap, sgp, b, binding.FP64, work, stream)
+        torch.cuda.synchronize()
+        pms = []
+        for _ in range(args.partial_steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            binding.pfaffian_partial(A0, tp, ipp, lap, sgp, b, binding.FP64, work, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            pms.append(e0.elapsed_time(e1))
+        pm = float(np.median(pms))
+        partial = {"n": n, "ms": pm, "speedup_vs_full": ms / pm,
+                   "sign_equal_full": int(sgp.item()) == sign64,
+                   "log_abs_pf_rel_diff_full":
+                       abs(float(lap.item()) - logpf64) / max(1.0, abs(logpf64))}
+        del tp, ipp
+        log(f"[bench] partial {partial}")
 
     # FP32-update variant
     fp32 = None
@@ -444,6 +472,7 @@ def main():
         "roofline": roof,
         "panel": panel,
         "solve": solve,
+        "pfaffian_partial": partial,
         "cpu_baseline": cpu,
         "kernels": kt,
         "fp32_update": fp32,

@@ -123,9 +123,10 @@ def batch_matrices(sizes, singular, seed: int):
 
 
 def serving_requests(count: int, seed: int, rate_per_s: float, lo: int = 32, hi: int = 2048,
-                     p_fp32: float = 0.5):
+                     p_fp32: float = 0.5, p_factor: float = 0.5):
     """Request stream: sizes, precision tags (0 = FP64, 1 = FP32 update),
-    arrival times (s) of a Poisson process with the given rate, and seeds."""
+    arrival times (s) of a Poisson process with the given rate, seeds, and
+    kinds (1 = factorization, 0 = Pfaffian only)."""
     rng = np.random.default_rng(seed)
     u = rng.uniform(np.log(lo), np.log(hi), count)
     sizes = 2 * np.round(np.exp(u) / 2.0).astype(np.int64)
@@ -134,4 +135,5 @@ def serving_requests(count: int, seed: int, rate_per_s: float, lo: int = 32, hi:
     gaps = rng.exponential(1.0 / rate_per_s, count)
     arrivals = np.cumsum(gaps)
     seeds = rng.integers(0, 2**31 - 1, count)
-    return sizes, prec, arrivals, seeds
+    kinds = (rng.uniform(0.0, 1.0, count) < p_factor).astype(np.int64)
+    return sizes, prec, arrivals, seeds, kinds

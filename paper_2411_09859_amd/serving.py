@@ -8,7 +8,10 @@ overlaps their work on the GPU:
 * small FP64 requests (n <= ``small_n``) are collected and factored together
   by one ``skltlt_batched`` launch; requests admitted while a batch runs join
   the next batch, which starts as soon as the batch stream is free;
-* the others run ``skltlt_pfaffian`` each, spread over a pool of streams.
+* the others run alone, spread over a pool of streams: a factorization
+  request by ``skltlt_pfaffian`` (its factors are handed back on the
+  device), a Pfaffian request by ``skltlt_pfaffian_partial`` (half the pivot
+  steps, nothing but the Pfaffian).
 
 Completion is detected by polling HIP events, never by blocking the device.
 Latency is measured from a request's arrival to the host observing its
@@ -39,7 +42,8 @@ class Request:
     arrival: float = 0.0          # seconds on the server clock
     seed: int = 0                 # for device-side generation of the input
     matrix: Optional[np.ndarray] = None  # host input (strict lower used), optional
-    want_factors: bool = False    # keep A/t/ipiv on the device for the caller
+    factor: bool = False          # factorization request: the factors (A, t, ipiv)
+                                  # come back on the device; else Pfaffian only
 
 
 @dataclasses.dataclass
@@ -107,10 +111,10 @@ class FakeExecutor:
         for _, reqs, path in done:
             for r in reqs:
                 if self.fail and self.fail(r):
-                    out.append((r, float("nan"), 0, path, "device error"))
+                    out.append((r, float("nan"), 0, path, "device error", None))
                     continue
                 la, sg = self.pf(r) if self.pf else (0.0, 1)
-                out.append((r, la, sg, path, None))
+                out.append((r, la, sg, path, None, None))
         return out
 
     def idle(self):
@@ -180,7 +184,8 @@ class GpuExecutor:
             ev = torch.cuda.Event()
             ev.record(s)
         keep = (mats, ts, ps, n_dev, lda, A_ptr, t_ptr, p_ptr, la, sg, info, work)
-        self.inflight.append((ev, ("batched", reqs, la_h, sg_h, keep)))
+        facs = [(mats[k], ts[k], ps[k]) if r.factor else None for k, r in enumerate(reqs)]
+        self.inflight.append((ev, ("batched", reqs, la_h, sg_h, keep, facs)))
 
     def launch_single(self, req):
         torch, binding = self.torch, self.binding
@@ -195,14 +200,19 @@ class GpuExecutor:
             sg = torch.empty(1, dtype=torch.int32, device=self.device)
             work = binding.alloc_workspace(
                 binding.workspace_size(max(n, 1), 0, req.precision), self.device)
-            binding.pfaffian(A, t, ip, la, sg, 0, req.precision, work, s)
+            if req.factor:
+                binding.pfaffian(A, t, ip, la, sg, 0, req.precision, work, s)
+            else:
+                binding.pfaffian_partial(A, t, ip, la, sg, 0, req.precision, work, s)
             la_h = torch.empty(1, dtype=torch.float64, pin_memory=True)
             sg_h = torch.empty(1, dtype=torch.int32, pin_memory=True)
             la_h.copy_(la, non_blocking=True)
             sg_h.copy_(sg, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        self.inflight.append((ev, ("single", [req], la_h, sg_h, (A, t, ip, la, sg, work))))
+        path = "single" if req.factor else "partial"
+        facs = [(A, t, ip)] if req.factor else [None]
+        self.inflight.append((ev, (path, [req], la_h, sg_h, (A, t, ip, la, sg, work), facs)))
 
     def batch_busy(self):
         return any(p[0] == "batched" for _, p in self.inflight)
@@ -211,9 +221,9 @@ class GpuExecutor:
         out, keep = [], []
         for ev, payload in self.inflight:
             if ev.query():
-                path, reqs, la_h, sg_h, bufs = payload
+                path, reqs, la_h, sg_h, bufs, facs = payload
                 for k, r in enumerate(reqs):
-                    out.append((r, float(la_h[k]), int(sg_h[k]), path, None))
+                    out.append((r, float(la_h[k]), int(sg_h[k]), path, None, facs[k]))
             else:
                 keep.append((ev, payload))
         self.inflight = keep
@@ -286,12 +296,12 @@ class Server:
 
     def _collect(self):
         now = self.clock()
-        for r, la, sg, path, err in self.ex.poll():
+        for r, la, sg, path, err, facs in self.ex.poll():
             self.used -= self.held.pop(r.rid)
-            if path == "single":
+            if path != "batched":
                 self.inflight_single -= 1
             self.results.append(Result(r.rid, r.n, la, sg, r.arrival,
-                                       self.admit_time.pop(r.rid), now, path, err))
+                                       self.admit_time.pop(r.rid), now, path, err, facs))
 
     def tick(self):
         self._collect()
@@ -337,12 +347,14 @@ def summarize(results, wall_s: float):
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "mean_ms": float(lat.mean() * 1e3),
         "batched_fraction": float(np.mean([r.path == "batched" for r in ok])) if ok else 0.0,
+        "partial_fraction": float(np.mean([r.path == "partial" for r in ok])) if ok else 0.0,
     }
 
 
-def make_requests(count: int, seed: int, rate_per_s: float, lo=32, hi=2048, p_fp32=0.5):
-    sizes, prec, arrivals, seeds = __import__(
+def make_requests(count: int, seed: int, rate_per_s: float, lo=32, hi=2048, p_fp32=0.5,
+                  p_factor=0.5):
+    sizes, prec, arrivals, seeds, kinds = __import__(
         "paper_2411_09859_amd.inputs", fromlist=["serving_requests"]).serving_requests(
-        count, seed, rate_per_s, lo, hi, p_fp32)
+        count, seed, rate_per_s, lo, hi, p_fp32, p_factor)
     return [Request(rid=k, n=int(sizes[k]), precision=int(prec[k]), arrival=float(arrivals[k]),
-                    seed=int(seeds[k])) for k in range(count)]
+                    seed=int(seeds[k]), factor=bool(kinds[k])) for k in range(count)]

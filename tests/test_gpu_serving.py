@@ -22,22 +22,35 @@ def serve(reqs, **kw):
 
 
 def test_alone_equals_mix_and_oracle():
+    """Factorization and Pfaffian requests of both paths (batched for
+    n <= 256, alone above: full factorization or the partial reduction)."""
     note("[serving] alone vs mix")
-    sizes = [32, 48, 100, 130, 256, 300, 520, 770, 34, 64, 1030, 200]
+    sizes = [32, 48, 100, 130, 256, 300, 520, 770, 34, 64, 1030, 200, 302, 1030]
     mats = [inputs.skew_normal(n, 500 + k) for k, n in enumerate(sizes)]
-    mix = [Request(k, n, precision=0, arrival=0.0, matrix=M) for k, (n, M) in
+    kind = [k % 2 == 0 for k in range(len(sizes))]  # True: factorization request
+    mix = [Request(k, n, precision=0, arrival=0.0, matrix=M, factor=kind[k]) for k, (n, M) in
            enumerate(zip(sizes, mats))]
     got, srv = serve(mix)
     assert len(got) == len(sizes) and srv.used == 0
     for k, M in enumerate(mats):
-        alone, _ = serve([Request(k, sizes[k], arrival=0.0, matrix=M)])
+        n = sizes[k]
+        alone, _ = serve([Request(k, n, arrival=0.0, matrix=M, factor=kind[k])])
         a, b = alone[k], got[k]
+        assert a.path == b.path
+        assert b.path == ("batched" if n <= 256 else ("single" if kind[k] else "partial"))
         assert a.sign == b.sign
         assert a.log_abs_pf == b.log_abs_pf  # bitwise: no dependence on the mix
         ref = oracle.ltlt(M)
-        la, sg = oracle.pfaffian(sizes[k], ref["t"], ref["ipiv"])
+        la, sg = oracle.pfaffian(n, ref["t"], ref["ipiv"])
         assert b.sign == sg
         assert abs(b.log_abs_pf - la) <= 1e-12 * max(1.0, abs(la))
+        if kind[k]:
+            A_d, t_d, ip_d = b.factors
+            assert np.array_equal(ip_d.cpu().numpy()[:n], ref["ipiv"])
+            assert np.linalg.norm(t_d.cpu().numpy()[: n - 1] - ref["t"]) <= \
+                1e-12 * np.linalg.norm(ref["t"])
+        else:
+            assert b.factors is None
 
 
 def test_poisson_stream_completes():
