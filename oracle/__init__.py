@@ -58,7 +58,7 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         lib.oracle_ltlt.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, ip,
-                                    ctypes.c_int, ctypes.c_int, ctypes.c_int]
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         lib.oracle_ltlt.restype = ctypes.c_int
         lib.oracle_pfaffian.argtypes = [ctypes.c_int, dp, ip, dp, ip, ctypes.c_int]
         lib.oracle_pfaffian.restype = ctypes.c_int
@@ -79,13 +79,16 @@ def _ip(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
 
 
-def ltlt(A: np.ndarray, max_steps: int = -1, nthreads: int = 0, mutation: int | str = 0):
+def ltlt(A: np.ndarray, max_steps: int = -1, nthreads: int = 0, mutation: int | str = 0,
+         pivot: bool = True):
     """Factor the skew matrix whose strict lower triangle is ``A`` (n x n).
 
     Returns a dict with ``X`` (state after the steps; T when complete), ``L``
     (unit lower, first column e_0), ``t`` (n-1 subdiagonal entries of T) and
     ``ipiv`` (absolute, 0-based, ipiv[0] = 0).  The relation P A P^T = L T L^T
-    holds with P built from ``ipiv`` by :func:`perm_from_ipiv`.
+    holds with P built from ``ipiv`` by :func:`perm_from_ipiv`.  With
+    ``pivot=False`` every step pivots on its own subdiagonal entry (P = I),
+    the unpivoted algorithm for inputs known to need no pivoting.
     """
     if isinstance(mutation, str):
         mutation = MUTATIONS[mutation]
@@ -97,7 +100,7 @@ def ltlt(A: np.ndarray, max_steps: int = -1, nthreads: int = 0, mutation: int | 
     t = np.zeros(max(n - 1, 1), dtype=np.float64)
     ipiv = np.zeros(max(n, 1), dtype=np.int32)
     rc = _load().oracle_ltlt(n, _dp(A), max(n, 1), _dp(X), _dp(L), _dp(t), _ip(ipiv),
-                             int(max_steps), int(nthreads), int(mutation))
+                             int(max_steps), int(bool(pivot)), int(nthreads), int(mutation))
     if rc != 0:
         raise ValueError(f"oracle_ltlt failed with status {rc}")
     return {"X": X, "L": L, "t": t[: max(n - 1, 0)], "ipiv": ipiv[:n]}

@@ -66,7 +66,7 @@ enum {
 };
 
 int oracle_ltlt(int n, const double *A, int lda, double *X, double *L,
-                double *t, int *ipiv, int max_steps, int nthreads,
+                double *t, int *ipiv, int max_steps, int pivot, int nthreads,
                 int mutation)
 {
     if (n < 0 || lda < (n > 1 ? n : 1) || (n > 0 && (!A || !X || !L || !ipiv)))
@@ -130,7 +130,9 @@ int oracle_ltlt(int n, const double *A, int lda, double *X, double *L,
                 p = i;
             }
         }
-        if (mutation == MUT_NO_PIVOTING)
+        /* Without pivoting (the unpivoted algorithms of Sec. 3.5 and 3.6,
+         * for inputs known to need none) the pivot row is always r. */
+        if (!pivot || mutation == MUT_NO_PIVOTING)
             p = r;
         ipiv[r] = p;
 

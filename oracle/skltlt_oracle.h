@@ -20,11 +20,13 @@ extern "C" {
  *   ipiv (out, n): absolute, 0-based, ipiv[0] = 0, ipiv[i] >= i.
  *   max_steps: < 0 for the whole factorization, else stop after that many
  *        column steps (X then holds the partially reduced matrix).
+ *   pivot: 1 for partial pivoting (Sec. 3.7), 0 for none (Sec. 3.5-3.6:
+ *        every step pivots on its own subdiagonal entry; ipiv[i] = i).
  *   nthreads: OpenMP threads for the trailing update (<= 0: default).
  *   mutation: 0 for the oracle; non-zero values plant known mistakes and are
  *        used only by the tests of the pins. */
 int oracle_ltlt(int n, const double *A, int lda, double *X, double *L,
-                double *t, int *ipiv, int max_steps, int nthreads,
+                double *t, int *ipiv, int max_steps, int pivot, int nthreads,
                 int mutation);
 
 /* Pf(A) = det(P) * prod_i (-t[2i]) as log|Pf| and sign in {-1, 0, +1}.

@@ -91,6 +91,24 @@ def skew_zero_line(n: int, seed: int, full: bool = True) -> np.ndarray:
     return A
 
 
+def skew_known_factor(n: int, seed: int, lmax: float = 0.9, full: bool = True):
+    """A = L0 T0 L0^T with unit lower L0 (first column e_0, entries below
+    the diagonal uniform in [-lmax, lmax] / sqrt(n)) and skew tridiagonal T0
+    with |t0| uniform in [1, 1.01] and random signs.  Returns (A, L0, t0): a
+    matrix whose factors without pivoting are known in advance (with lmax
+    above 1/2 partial pivoting would exchange rows, without it the factors
+    are L0 and t0)."""
+    rng = np.random.default_rng(seed)
+    L0 = np.tril(rng.uniform(-lmax, lmax, (n, n)) / np.sqrt(max(n, 1)), -1)
+    L0[:, 0] = 0.0
+    L0 += np.eye(n)
+    t0 = rng.uniform(1.0, 1.01, max(n - 1, 0)) * rng.choice([-1.0, 1.0], max(n - 1, 0))
+    T0 = np.diag(t0, -1) - np.diag(t0, 1) if n > 1 else np.zeros((n, n))
+    A = L0 @ T0 @ L0.T
+    A = np.asfortranarray(A if full else np.tril(A, -1))
+    return A, L0, t0
+
+
 def batch_sizes(count: int, seed: int, lo: int = 16, hi: int = 256,
                 singular_fraction: float = 0.05):
     """Even sizes uniform over [lo, hi] and a seeded set of singular members.

@@ -260,6 +260,56 @@ def test_planted_mistake_is_caught(mutation):
     assert _pin_failures(mutation), f"mutation {mutation} escaped every pin"
 
 
+# ------------------------------------------------------ unpivoted (P = I)
+# The unpivoted algorithm (Sec. 3.5-3.6 without the pivoting of Sec. 3.7) is
+# pinned by matrices built from known factors: the factorization is unique
+# (Sec. 3.2), so without exchanges it must return L0 and t0.
+def _known(n, seed, lmax, scaled=True):
+    rng = np.random.default_rng(seed)
+    L0 = np.tril(rng.uniform(-lmax, lmax, (n, n)) / (np.sqrt(n) if scaled else 1.0), -1)
+    L0[:, 0] = 0.0
+    L0 += np.eye(n)
+    t0 = rng.uniform(1.0, 1.01, n - 1) * rng.choice([-1.0, 1.0], n - 1)
+    T0 = np.diag(t0, -1) - np.diag(t0, 1)
+    return L0 @ T0 @ L0.T, L0, t0
+
+
+@pytest.mark.parametrize("n,lmax", [(8, 0.9), (64, 0.9), (200, 2.0)])
+def test_nopiv_known_factors_recovered(n, lmax):
+    A, L0, t0 = _known(n, n, lmax)
+    res = oracle.ltlt(A, pivot=False)
+    assert np.array_equal(res["ipiv"], np.arange(n))
+    assert np.linalg.norm(res["L"] - L0) <= 1e-12 * np.linalg.norm(L0)
+    assert np.linalg.norm(res["t"] - t0) <= 1e-12 * np.linalg.norm(t0)
+
+
+def test_nopiv_differs_from_pivoting():
+    """Entries of L0 above 1: partial pivoting exchanges rows, the unpivoted
+    algorithm still returns L0 and t0."""
+    A, L0, t0 = _known(8, 3, 4.0, scaled=False)
+    assert np.any(oracle.ltlt(A)["ipiv"] != np.arange(8))
+    res = oracle.ltlt(A, pivot=False)
+    assert np.array_equal(res["ipiv"], np.arange(8))
+    assert np.linalg.norm(res["L"] - L0) <= 1e-12 * np.linalg.norm(L0)
+    assert np.linalg.norm(res["t"] - t0) <= 1e-12 * np.linalg.norm(t0)
+
+
+@pytest.mark.parametrize("n", [4, 6, 8, 10])
+def test_nopiv_pf_brute_force(n):
+    A, _, _ = _known(n, 40 + n, 2.0, scaled=False)
+    res = oracle.ltlt(A, pivot=False)
+    assert pf_value(res, n) == pytest.approx(ck.pf_expand(A), rel=1e-10)
+
+
+@pytest.mark.parametrize("mutation", ["drop_second_term", "l_from_upper", "wrong_l_column"])
+def test_nopiv_planted_mistake_is_caught(mutation):
+    A, L0, t0 = _known(12, 5, 2.0, scaled=False)
+    res = oracle.ltlt(A, pivot=False, mutation=mutation)
+    ok = (np.linalg.norm(res["L"] - L0) <= 1e-12 * np.linalg.norm(L0)
+          and np.linalg.norm(res["t"] - t0) <= 1e-12 * np.linalg.norm(t0))
+    assert not ok
+
+
 # ------------------------------------------- Pfaffian-only ("partial") reduction
 # Wimmer's algorithm (Sec. 3.5.2 Notes, Sec. 3.6.5 Note): one pivot and one
 # rank-2 Schur complement per pair of columns.  Pinned by the Pfaffian's
