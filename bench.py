@@ -240,6 +240,8 @@ def main():
                     help="timed solves with the factors (0: skip)")
     ap.add_argument("--partial-steps", type=int, default=2,
                     help="timed Pfaffian-only (partial) reductions (0: skip)")
+    ap.add_argument("--nopiv-steps", type=int, default=2,
+                    help="timed unpivoted factorizations of a known-factor matrix (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -367,6 +369,48 @@ def main():
         del tp, ipp
         log(f"[bench] partial {partial}")
 
+    # unpivoted factorization (for inputs that need no pivoting) on a matrix
+    # assembled from known factors, A = L0 T0 L0^T, of the same order
+    nopiv = None
+    if args.nopiv_steps > 0:
+        g = torch.Generator(device=dev)
+        g.manual_seed(args.seed + 11)
+        L0 = torch.tril((torch.rand((n, n), generator=g, dtype=torch.float64, device=dev) * 2 - 1)
+                        * (2.0 / n ** 0.5), -1)
+        L0[:, 0] = 0
+        L0 += torch.eye(n, dtype=torch.float64, device=dev)
+        t0 = (1.0 + 0.01 * torch.rand(n - 1, generator=g, dtype=torch.float64, device=dev)) * \
+            torch.where(torch.rand(n - 1, generator=g, device=dev) < 0.5, -1.0, 1.0).double()
+        K = torch.diag(t0, -1) - torch.diag(t0, 1)
+        K = (L0 @ K) @ L0.T.contiguous()
+        del L0
+        Kc = K.T.contiguous().T
+        del K
+        bn = min(b, 128)
+        tn = torch.zeros_like(t)
+        ipn = torch.zeros_like(ipiv)
+        lan = torch.zeros_like(la)
+        sgn = torch.zeros_like(sg)
+        nms = []
+        for s_ in range(args.nopiv_steps + 1):
+            Aw.copy_(Kc)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            binding.pfaffian_nopiv(Aw, tn, ipn, lan, sgn, bn, binding.FP64, work, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if s_ > 0:  # the first run is the warmup
+                nms.append(e0.elapsed_time(e1))
+        nm = float(np.mean(nms))
+        nopiv = {"workload": f"n={n} A = L0 T0 L0^T, |L0| <= 2/sqrt(n), |t0| in [1, 1.01]",
+                 "block": bn, "ms": nm, "gflops_nominal": nominal / (nm * 1e-3) / 1e9,
+                 "frac_fp64_peak": nominal / (nm * 1e-3) / 78.6e12,
+                 "t_rel_err_vs_t0": (torch.linalg.norm(tn - t0) / torch.linalg.norm(t0)).item()}
+        del Kc, tn, ipn, t0
+        log(f"[bench] nopiv {nopiv}")
+
     # FP32-update variant
     fp32 = None
     if args.fp32_steps > 0:
@@ -473,6 +517,7 @@ def main():
         "panel": panel,
         "solve": solve,
         "pfaffian_partial": partial,
+        "nopiv": nopiv,
         "cpu_baseline": cpu,
         "kernels": kt,
         "fp32_update": fp32,

@@ -105,6 +105,27 @@ int skltlt_pfaffian(int n, double *A, int lda, double *t, int *ipiv,
                     int precision, void *work, size_t work_bytes,
                     void *stream);
 
+/* The unpivoted factorization A = L T L^T (P = I): the blocked fused
+ * algorithm of Sec. 3.6.3 without the pivoting of Sec. 3.7, for inputs known
+ * to need none (e.g. matrices assembled from well-conditioned factors); on
+ * other inputs it may divide by small or zero t (no error is raised: a zero
+ * t[k] gives a zero column of L, as in the pivoted algorithm).  Without
+ * exchanges each panel's dependent steps involve only its top rows: one
+ * workgroup runs them and every other row follows independently.
+ * Arguments, layout, workspace and errors as for skltlt_factor, with
+ * ipiv[i] = i on return (so the result can be passed to skltlt_solve);
+ * block_size 0 means 128, and widths above 128 are reduced to 128. */
+int skltlt_factor_nopiv(int n, double *A, int lda, double *t, int *ipiv,
+                        int block_size, int precision, void *work,
+                        size_t work_bytes, void *stream);
+
+/* skltlt_factor_nopiv followed by the Pfaffian, Pf(A) = prod_i (-t[2i]);
+ * arguments as for skltlt_pfaffian. */
+int skltlt_pfaffian_nopiv(int n, double *A, int lda, double *t, int *ipiv,
+                          double *log_abs_pf, int *sign, int block_size,
+                          int precision, void *work, size_t work_bytes,
+                          void *stream);
+
 /* Pfaffian only, by the "partial" reduction (Wimmer's algorithm: the
  * two-step algorithm of Sec. 3.5.2 with the second Gauss transform of each
  * pair and its tau skipped, Sec. 3.5.2 Notes; blocked with accumulated

@@ -58,6 +58,10 @@ def lib():
         L.skltlt_factor.restype = i
         L.skltlt_pfaffian.argtypes = [i, vp, i, vp, vp, vp, vp, i, i, vp, sz, vp]
         L.skltlt_pfaffian.restype = i
+        L.skltlt_factor_nopiv.argtypes = [i, vp, i, vp, vp, i, i, vp, sz, vp]
+        L.skltlt_factor_nopiv.restype = i
+        L.skltlt_pfaffian_nopiv.argtypes = [i, vp, i, vp, vp, vp, vp, i, i, vp, sz, vp]
+        L.skltlt_pfaffian_nopiv.restype = i
         L.skltlt_pfaffian_partial.argtypes = [i, vp, i, vp, vp, vp, vp, i, i, vp, sz, vp]
         L.skltlt_pfaffian_partial.restype = i
         L.skltlt_batched_max_n.argtypes = []
@@ -148,6 +152,36 @@ def pfaffian(A, t, ipiv, log_abs_pf, sign, block_size: int = 0, precision: int =
                                work.numel(), _stream(stream))
     if st != SKLTLT_OK:
         raise SkltltError(st, "skltlt_pfaffian")
+    return st
+
+
+def factor_nopiv(A, t, ipiv, block_size: int = 0, precision: int = FP64, work=None,
+                 stream=None):
+    """skltlt_factor_nopiv (no pivoting) on device tensors; ipiv receives the
+    identity."""
+    n = A.shape[0]
+    lda = _lda_of(A)
+    if work is None:
+        work = alloc_workspace(workspace_size(n, block_size, precision), A.device)
+    st = lib().skltlt_factor_nopiv(n, _ptr(A), lda, _ptr(t), _ptr(ipiv), int(block_size),
+                                   int(precision), _ptr(work), work.numel(), _stream(stream))
+    if st != SKLTLT_OK:
+        raise SkltltError(st, "skltlt_factor_nopiv")
+    return st
+
+
+def pfaffian_nopiv(A, t, ipiv, log_abs_pf, sign, block_size: int = 0, precision: int = FP64,
+                   work=None, stream=None):
+    """skltlt_pfaffian_nopiv on device tensors."""
+    n = A.shape[0]
+    lda = _lda_of(A)
+    if work is None:
+        work = alloc_workspace(workspace_size(n, block_size, precision), A.device)
+    st = lib().skltlt_pfaffian_nopiv(n, _ptr(A), lda, _ptr(t), _ptr(ipiv), _ptr(log_abs_pf),
+                                     _ptr(sign), int(block_size), int(precision), _ptr(work),
+                                     work.numel(), _stream(stream))
+    if st != SKLTLT_OK:
+        raise SkltltError(st, "skltlt_pfaffian_nopiv")
     return st
 
 

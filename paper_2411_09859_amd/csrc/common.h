@@ -72,6 +72,14 @@ hipError_t launch_panel(double *A, int lda, const double *W, int n, int k0, int 
 hipError_t launch_panel_pair(const double *W, int n, int k0, int nb, int b, double *t, int *ipiv,
                              const FactorWs &ws, int want32, const PanelShape &sh, hipStream_t s);
 
+// Unpivoted panel (top rows, then all other rows), nb <= nopiv_max_block().
+hipError_t launch_nopiv_panel(double *A, int lda, const double *W, int n, int k0, int nb,
+                              double *t, const FactorWs &ws, int want32, hipStream_t s);
+int nopiv_max_block();
+void nopiv_init_attrs();
+// p[i] = i for i < n
+hipError_t launch_iota(int *p, int n, hipStream_t s);
+
 // Wn[i][j] = Wc[perm[i]][perm[j]] - (U V^T - V U^T)[i][j] for i != j >= cp.
 hipError_t launch_skr2k(const double *Wc, double *Wn, int n, int cp, int nq,
                         const FactorWs &ws, int precision, hipStream_t s);

@@ -86,6 +86,7 @@ static void init_device_attrs()
     std::call_once(once, [] {
         panel_init_attrs();
         finalize_init_attrs();
+        nopiv_init_attrs();
         solve_init_attrs();
         (void)hipGetLastError();
     });
@@ -148,8 +149,10 @@ extern "C" int skltlt_workspace_size(int n, int block_size, int precision, size_
     return SKLTLT_OK;
 }
 
+// pivot = 0: the unpivoted algorithm (panel width at most nopiv_max_block()).
 static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int block_size,
-                       int precision, void *work, size_t work_bytes, hipStream_t s)
+                       int precision, void *work, size_t work_bytes, hipStream_t s,
+                       bool pivot = true)
 {
     if (n < 0 || lda < (n > 1 ? n : 1) || block_size < 0)
         return SKLTLT_EINVAL;
@@ -159,25 +162,30 @@ static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int bloc
         return SKLTLT_EINVAL;
     if (n >= 2 && !t)
         return SKLTLT_EINVAL;
-    const int b = resolve_block(n, block_size);
-    int st = check_supported(n, b);
+    const int b0 = resolve_block(n, block_size);
+    int st = check_supported(n, b0);
     if (st != SKLTLT_OK)
         return st;
     if (n == 0)
         return SKLTLT_OK;
-    const size_t need = factor_ws_layout(n, b, nullptr, nullptr);
+    // the workspace is laid out for the requested width (what the size
+    // query reports); the unpivoted panel may use a narrower one
+    const size_t need = factor_ws_layout(n, b0, nullptr, nullptr);
+    const int b = pivot ? b0 : (b0 < nopiv_max_block() ? b0 : nopiv_max_block());
     if (!work || work_bytes < need || ((uintptr_t)work % kAlign) != 0)
         return SKLTLT_EINVAL;
     init_device_attrs();
 
     FactorWs ws;
-    factor_ws_layout(n, b, &ws, (char *)work);
+    factor_ws_layout(n, b0, &ws, (char *)work);
 
     {
         const int ti = tm_begin(SKLTLT_K_OTHER, s);
-        hipError_t e = launch_set_int(ipiv, 0, s);
+        hipError_t e = pivot ? launch_set_int(ipiv, 0, s) : launch_iota(ipiv, n, s);
         if (e != hipSuccess)
-            return device_error(e, "set ipiv[0]");
+            return device_error(e, "set ipiv");
+        if (!pivot && (e = launch_iota(ws.perm, n, s)) != hipSuccess)
+            return device_error(e, "identity permutation");
         if (n > 1 && (e = launch_fill_zero(ws.slots, (size_t)kSlotBytes * 2 * kSlotsPerParity, s)) !=
                          hipSuccess)
             return device_error(e, "clear slots");
@@ -190,19 +198,27 @@ static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int bloc
 
     const int want32 = (precision == SKLTLT_FP32_UPDATE);
     // panel geometry: as many groups as the device keeps resident
-    PanelShape probe = panel_shape(n, 0, b, kMaxPanelGroups);
-    int maxg = panel_max_groups(probe.lds, false);
-    if (maxg <= 0)
-        return device_error(hipErrorInvalidValue, "panel occupancy query");
+    int maxg = 0;
+    if (pivot) {
+        PanelShape probe = panel_shape(n, 0, b, kMaxPanelGroups);
+        maxg = panel_max_groups(probe.lds, false);
+        if (maxg <= 0)
+            return device_error(hipErrorInvalidValue, "panel occupancy query");
+    }
 
     int cur = 0; // W buffer holding the current trailing matrix
     for (int k0 = 0; k0 < n - 1; k0 += b) {
         const int nb = (b < n - 1 - k0) ? b : (n - 1 - k0);
-        PanelShape sh = panel_shape(n, k0, b, maxg);
-        if (sh.lds > kLdsCap || sh.G > maxg || 8L * sh.G > 8L * maxg)
-            return SKLTLT_ENOTSUP;
         int ti = tm_begin(SKLTLT_K_PANEL, s);
-        hipError_t e = launch_panel(A, lda, ws.W[cur], n, k0, nb, b, t, ipiv, ws, want32, sh, s);
+        hipError_t e;
+        if (pivot) {
+            PanelShape sh = panel_shape(n, k0, b, maxg);
+            if (sh.lds > kLdsCap || sh.G > maxg || 8L * sh.G > 8L * maxg)
+                return SKLTLT_ENOTSUP;
+            e = launch_panel(A, lda, ws.W[cur], n, k0, nb, b, t, ipiv, ws, want32, sh, s);
+        } else {
+            e = launch_nopiv_panel(A, lda, ws.W[cur], n, k0, nb, t, ws, want32, s);
+        }
         if (e != hipSuccess)
             return device_error(e, "panel launch");
         tm_end(ti, s, 0.0);
@@ -219,7 +235,7 @@ static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int bloc
             tm_end(ti, s, m * (m - 1.0) * 0.5 * 2.0 * (2.0 * nq));
         }
     }
-    {
+    if (pivot) {
         const int ti = tm_begin(SKLTLT_K_FINALIZE, s);
         hipError_t e = launch_finalize(A, lda, n, b, ipiv, ws, s);
         if (e != hipSuccess)
@@ -244,6 +260,32 @@ extern "C" int skltlt_pfaffian(int n, double *A, int lda, double *t, int *ipiv,
         return SKLTLT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     int st = factor_impl(n, A, lda, t, ipiv, block_size, precision, work, work_bytes, s);
+    if (st != SKLTLT_OK)
+        return st;
+    const int ti = tm_begin(SKLTLT_K_PFAFFIAN, s);
+    hipError_t e = launch_pfaffian(n, t, ipiv, log_abs_pf, sign, s);
+    if (e != hipSuccess)
+        return device_error(e, "pfaffian launch");
+    tm_end(ti, s, 0.0);
+    return SKLTLT_OK;
+}
+
+extern "C" int skltlt_factor_nopiv(int n, double *A, int lda, double *t, int *ipiv,
+                                   int block_size, int precision, void *work, size_t work_bytes,
+                                   void *stream)
+{
+    return factor_impl(n, A, lda, t, ipiv, block_size, precision, work, work_bytes,
+                       (hipStream_t)stream, false);
+}
+
+extern "C" int skltlt_pfaffian_nopiv(int n, double *A, int lda, double *t, int *ipiv,
+                                     double *log_abs_pf, int *sign, int block_size, int precision,
+                                     void *work, size_t work_bytes, void *stream)
+{
+    if (!log_abs_pf || !sign)
+        return SKLTLT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int st = factor_impl(n, A, lda, t, ipiv, block_size, precision, work, work_bytes, s, false);
     if (st != SKLTLT_OK)
         return st;
     const int ti = tm_begin(SKLTLT_K_PFAFFIAN, s);

@@ -1,0 +1,156 @@
+"""GPU parity of the unpivoted factorization (skltlt_factor_nopiv /
+skltlt_pfaffian_nopiv) against the oracle without pivoting, on matrices
+assembled from known factors (A = L0 T0 L0^T, the inputs the unpivoted
+algorithm is meant for).
+
+Bar (FP64): ipiv the identity; ||t - t_oracle|| / ||t_oracle|| and
+||L - L_oracle||_F / ||L_oracle||_F <= 1e-12; reconstruction residual
+||A - L T L^T||_F / ||A||_F <= 1e-12; the diagonal and upper triangle of A
+bit-for-bit untouched; Pfaffian sign equal and |log|Pf| - log|Pf|_oracle| <=
+1e-12 * max(1, |log|Pf||).  At n = 8192 and 16384 (too large for the oracle)
+the factors are compared with the known L0, t0 and the Pfaffian with
+prod(-t0[2i]).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_09859_amd import binding, inputs
+from tests import checkers as ck
+from tests.gpu_util import note, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def run_nopiv(A_np, block_size=0, precision=binding.FP64, lda=None):
+    import torch
+    n = A_np.shape[0]
+    lda = n if lda is None else lda
+    buf = np.zeros((max(lda, 1), max(n, 1)), dtype=np.float64, order="F")
+    buf[:] = 7.25
+    buf[:n, :n] = A_np
+    dev = torch.from_numpy(buf).to("cuda")
+    Adev = dev[:n, :n] if n > 0 else dev[:0, :0]
+    t = torch.zeros(max(n - 1, 1), dtype=torch.float64, device="cuda")
+    ipiv = torch.full((max(n, 1),), -1, dtype=torch.int32, device="cuda")
+    la = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sg = torch.full((1,), 9, dtype=torch.int32, device="cuda")
+    work = binding.alloc_workspace(binding.workspace_size(max(n, 1), block_size, precision))
+    binding.pfaffian_nopiv(Adev, t, ipiv, la, sg, block_size, precision, work)
+    torch.cuda.synchronize()
+    hbuf = np.asfortranarray(dev.cpu().numpy())
+    return {"buf": hbuf, "A": np.asfortranarray(hbuf[:n, :n]),
+            "t": t.cpu().numpy()[: max(n - 1, 0)], "ipiv": ipiv.cpu().numpy()[:n],
+            "log_abs_pf": float(la.cpu().numpy()[0]), "sign": int(sg.cpu().numpy()[0])}
+
+
+def check(A, res, tol=TOL):
+    n = A.shape[0]
+    ref = oracle.ltlt(A, pivot=False)
+    assert np.array_equal(res["ipiv"], np.arange(n))
+    if n >= 2:
+        assert rel(res["t"], ref["t"]) <= tol
+        L, t = ck.unpack(res["A"], n)
+        assert np.array_equal(t, res["t"])
+        assert rel(L, ref["L"]) <= tol
+        assert ck.residual(A, L, t, res["ipiv"]) <= tol
+    assert np.array_equal(np.triu(res["A"]), np.triu(A))
+    la, sg = oracle.pfaffian(n, ref["t"], ref["ipiv"])
+    assert res["sign"] == sg
+    if sg != 0:
+        assert abs(res["log_abs_pf"] - la) <= tol * max(1.0, abs(la))
+
+
+CASES = [(2, 0), (3, 0), (5, 1), (16, 2), (17, 3), (64, 16), (65, 0), (130, 32), (200, 64),
+         (257, 0), (300, 128), (513, 256), (1000, 0), (2048, 128), (2049, 64)]
+
+
+@pytest.mark.parametrize("n,b", CASES)
+def test_nopiv_parity(n, b):
+    note(f"[nopiv] n={n} b={b}")
+    A, _, _ = inputs.skew_known_factor(n, 3000 + n, 2.0)
+    check(A, run_nopiv(A, block_size=b))
+
+
+def test_nopiv_padding_untouched():
+    note("[nopiv] lda > n")
+    A, _, _ = inputs.skew_known_factor(300, 9, 2.0)
+    res = run_nopiv(A, block_size=64, lda=333)
+    check(A, res)
+    assert np.all(res["buf"][300:, :] == 7.25)
+
+
+def test_nopiv_fp32_update():
+    n = 1024
+    note(f"[nopiv] fp32 n={n}")
+    A, L0, t0 = inputs.skew_known_factor(n, 21, 2.0)
+    res = run_nopiv(A, precision=binding.FP32_UPDATE)
+    L, t = ck.unpack(res["A"], n)
+    assert ck.residual(A, L, t, res["ipiv"]) <= math.sqrt(n) * 1e-7
+    ref = oracle.ltlt(A, pivot=False)
+    la, sg = oracle.pfaffian(n, ref["t"], ref["ipiv"])
+    assert res["sign"] == sg and abs(res["log_abs_pf"] - la) <= 1e-4 * max(1.0, abs(la))
+
+
+def test_nopiv_solve():
+    """The unpivoted factors (ipiv = identity) serve skltlt_solve."""
+    import torch
+    n = 600
+    note(f"[nopiv] solve n={n}")
+    A, _, _ = inputs.skew_known_factor(n, 23, 2.0)
+    Ad = binding.to_device_colmajor(A)
+    t = torch.zeros(n - 1, dtype=torch.float64, device="cuda")
+    ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    binding.factor_nopiv(Ad, t, ipiv)
+    w = np.random.default_rng(1).standard_normal(n)
+    x = torch.from_numpy(w.copy()).to("cuda")
+    binding.solve(Ad, t, ipiv, x)
+    torch.cuda.synchronize()
+    xh = x.cpu().numpy()
+    low = np.tril(A, -1)
+    Af = low - low.T
+    back = np.linalg.norm(Af @ xh - w) / (np.linalg.norm(Af) * np.linalg.norm(xh))
+    assert back <= 1e-13
+
+
+@pytest.mark.parametrize("n,b", [(8192, 128), (16384, 128), (16384, 64)])
+def test_nopiv_full_size_known_factors(n, b):
+    import torch
+    note(f"[nopiv] full size n={n} b={b}")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(n + b)
+    L0 = torch.tril((torch.rand((n, n), generator=g, dtype=torch.float64, device="cuda") * 2 - 1)
+                    * (2.0 / math.sqrt(n)), -1)
+    L0[:, 0] = 0
+    L0 += torch.eye(n, dtype=torch.float64, device="cuda")
+    t0 = (1.0 + 0.01 * torch.rand(n - 1, generator=g, dtype=torch.float64, device="cuda")) * \
+        torch.where(torch.rand(n - 1, generator=g, device="cuda") < 0.5, -1.0, 1.0).double()
+    T0 = torch.diag(t0, -1) - torch.diag(t0, 1)
+    A = (L0 @ T0) @ L0.T.contiguous()
+    del T0
+    Af = A.T.contiguous().T
+    del A
+    t = torch.zeros(n - 1, dtype=torch.float64, device="cuda")
+    ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    la = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sg = torch.zeros(1, dtype=torch.int32, device="cuda")
+    binding.pfaffian_nopiv(Af, t, ipiv, la, sg, b)
+    torch.cuda.synchronize()
+    assert torch.equal(ipiv.cpu(), torch.arange(n, dtype=torch.int32))
+    et = (torch.linalg.norm(t - t0) / torch.linalg.norm(t0)).item()
+    L = torch.roll(torch.tril(Af, -2), shifts=1, dims=1)
+    L[:, 0] = 0
+    L += torch.eye(n, dtype=torch.float64, device="cuda")
+    eL = (torch.linalg.norm(L - L0) / torch.linalg.norm(L0)).item()
+    note(f"[nopiv] n={n} |t - t0| {et:.2e} |L - L0| {eL:.2e}")
+    assert et <= TOL and eL <= TOL
+    want_la = torch.sum(torch.log(torch.abs(t0[0::2]))).item()
+    want_sg = int(torch.prod(torch.sign(-t0[0::2])).item())
+    assert int(sg.item()) == want_sg
+    assert abs(la.item() - want_la) <= TOL * max(1.0, abs(want_la))
