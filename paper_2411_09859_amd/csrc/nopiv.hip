@@ -180,7 +180,6 @@ __global__ __launch_bounds__(kNpNT) void nopiv_top_kernel(
     extern __shared__ double ltop[]; // nb x (nb + 2): the top rows' L, row-major
     const int ldt = nb + 2;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
     const int lr = tid / kNpTPR;
     const int sub = tid - lr * kNpTPR;
     const int base = k0 + 1;
@@ -276,7 +275,6 @@ __global__ __launch_bounds__(kNpNT) void nopiv_rows_kernel(
     __shared__ double tl[kNpMaxB];
     __shared__ double rtl[kNpMaxB]; // 1 / t (0 where t = 0)
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
     const int lr = tid / kNpTPR;
     const int sub = tid - lr * kNpTPR;
     const int cp = k0 + nb;
@@ -348,28 +346,44 @@ void nopiv_init_attrs()
 
 int nopiv_max_block() { return kNpMaxB; }
 
-hipError_t launch_nopiv_panel(double *A, int lda, const double *W, int n, int k0, int nb,
-                              double *t, const FactorWs &ws, int want32, hipStream_t s)
+static hipError_t launch_nopiv_top(double *A, int lda, const double *W, int n, int k0, int nb,
+                                   double *t, const FactorWs &ws, int want32, hipStream_t s)
 {
     if (nb < 1 || nb > kNpMaxB)
         return hipErrorInvalidValue;
     (void)hipGetLastError();
-    const int ldh = NpRow::NA;
-    double *H = ws.mirror; // nb x ldh
     hipLaunchKernelGGL(nopiv_top_kernel, dim3(1), dim3(kNpNT), nopiv_top_lds(nb), s, A, lda, W,
-                       ws.ldw, n, k0, nb, t, ws.lcar, H, ldh, ws.uv, ws.uv32, want32);
-    hipError_t e = hipGetLastError();
+                       ws.ldw, n, k0, nb, t, ws.lcar, ws.mirror, (int)NpRow::NA, ws.uv, ws.uv32,
+                       want32);
+    return hipGetLastError();
+}
+
+static hipError_t launch_nopiv_rows(double *A, int lda, const double *W, int n, int k0, int nb,
+                                    const double *t, const FactorWs &ws, int want32,
+                                    hipStream_t s)
+{
+    if (nb < 1 || nb > kNpMaxB)
+        return hipErrorInvalidValue;
+    const int below = n - (k0 + nb + 1);
+    if (below <= 0)
+        return hipSuccess;
+    (void)hipGetLastError();
+    const dim3 grid((unsigned)((below + kNpR - 1) / kNpR));
+    hipLaunchKernelGGL(nopiv_rows_kernel, grid, dim3(kNpNT), nopiv_rows_lds(nb), s, A, lda, W,
+                       ws.ldw, n, k0, nb, t, ws.lcar, (const double *)ws.mirror, (int)NpRow::NA,
+                       ws.uv, ws.uv32, want32);
+    return hipGetLastError();
+}
+
+// The whole panel: the top rows (one workgroup; h and t into the mirror
+// buffer), then every other row.
+hipError_t launch_nopiv_panel(double *A, int lda, const double *W, int n, int k0, int nb,
+                              double *t, const FactorWs &ws, int want32, hipStream_t s)
+{
+    hipError_t e = launch_nopiv_top(A, lda, W, n, k0, nb, t, ws, want32, s);
     if (e != hipSuccess)
         return e;
-    const int below = n - (k0 + nb + 1);
-    if (below > 0) {
-        const dim3 grid((unsigned)((below + kNpR - 1) / kNpR));
-        hipLaunchKernelGGL(nopiv_rows_kernel, grid, dim3(kNpNT), nopiv_rows_lds(nb), s, A, lda, W,
-                           ws.ldw, n, k0, nb, (const double *)t, ws.lcar, (const double *)H, ldh,
-                           ws.uv, ws.uv32, want32);
-        e = hipGetLastError();
-    }
-    return e;
+    return launch_nopiv_rows(A, lda, W, n, k0, nb, t, ws, want32, s);
 }
 
 // perm[i] = i (the skr2k's gather becomes the identity)
