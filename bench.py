@@ -408,6 +408,25 @@ def main():
                  "block": bn, "ms": nm, "gflops_nominal": nominal / (nm * 1e-3) / 1e9,
                  "frac_fp64_peak": nominal / (nm * 1e-3) / 78.6e12,
                  "t_rel_err_vs_t0": (torch.linalg.norm(tn - t0) / torch.linalg.norm(t0)).item()}
+        # the same factorization by the left-looking algorithm
+        lwork = binding.alloc_workspace(binding.left_workspace_size(n, bn), dev)
+        lms = []
+        for s_ in range(args.nopiv_steps + 1):
+            Aw.copy_(Kc)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            binding.pfaffian_left(Aw, tn, ipn, lan, sgn, bn, lwork, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if s_ > 0:
+                lms.append(e0.elapsed_time(e1))
+        del lwork
+        lm = float(np.mean(lms))
+        nopiv["left_looking"] = {
+            "ms": lm, "gflops_nominal": nominal / (lm * 1e-3) / 1e9,
+            "t_rel_err_vs_t0": (torch.linalg.norm(tn - t0) / torch.linalg.norm(t0)).item()}
         del Kc, tn, ipn, t0
         log(f"[bench] nopiv {nopiv}")
 

@@ -126,6 +126,31 @@ int skltlt_pfaffian_nopiv(int n, double *A, int lda, double *t, int *ipiv,
                           int precision, void *work, size_t work_bytes,
                           void *stream);
 
+/* Bytes of device workspace for skltlt_factor_left / skltlt_pfaffian_left
+ * (the factorization's workspace plus the accumulated operands of the
+ * left-looking update, 2 * n * ~n doubles). */
+int skltlt_left_workspace_size(int n, int block_size, size_t *bytes);
+
+/* The unpivoted factorization by the blocked left-looking algorithm
+ * (Variant 3, Sec. 3.6.4, from Invariant 3 of Sec. 3.4): when a panel is
+ * reached, all earlier panels' skew rank-2k terms are applied to its
+ * columns only (skew_tridiag_gemm, Sec. 3.6.6), then the panel is factored
+ * as in skltlt_factor_nopiv; nothing right of the panel is touched.  Same
+ * result as skltlt_factor_nopiv in exact arithmetic (the split of the
+ * update's sum over workgroups uses floating-point atomics, so the last bits
+ * may differ between runs).  Arguments as for skltlt_factor_nopiv (ipiv[i] = i
+ * on return); precision must be SKLTLT_FP64 (SKLTLT_ENOTSUP otherwise);
+ * work_bytes >= skltlt_left_workspace_size(n, block_size). */
+int skltlt_factor_left(int n, double *A, int lda, double *t, int *ipiv,
+                       int block_size, int precision, void *work,
+                       size_t work_bytes, void *stream);
+
+/* skltlt_factor_left followed by the Pfaffian (as skltlt_pfaffian_nopiv). */
+int skltlt_pfaffian_left(int n, double *A, int lda, double *t, int *ipiv,
+                         double *log_abs_pf, int *sign, int block_size,
+                         int precision, void *work, size_t work_bytes,
+                         void *stream);
+
 /* Pfaffian only, by the "partial" reduction (Wimmer's algorithm: the
  * two-step algorithm of Sec. 3.5.2 with the second Gauss transform of each
  * pair and its tau skipped, Sec. 3.5.2 Notes; blocked with accumulated

@@ -58,6 +58,12 @@ def lib():
         L.skltlt_factor.restype = i
         L.skltlt_pfaffian.argtypes = [i, vp, i, vp, vp, vp, vp, i, i, vp, sz, vp]
         L.skltlt_pfaffian.restype = i
+        L.skltlt_left_workspace_size.argtypes = [i, i, ctypes.POINTER(sz)]
+        L.skltlt_left_workspace_size.restype = i
+        L.skltlt_factor_left.argtypes = [i, vp, i, vp, vp, i, i, vp, sz, vp]
+        L.skltlt_factor_left.restype = i
+        L.skltlt_pfaffian_left.argtypes = [i, vp, i, vp, vp, vp, vp, i, i, vp, sz, vp]
+        L.skltlt_pfaffian_left.restype = i
         L.skltlt_factor_nopiv.argtypes = [i, vp, i, vp, vp, i, i, vp, sz, vp]
         L.skltlt_factor_nopiv.restype = i
         L.skltlt_pfaffian_nopiv.argtypes = [i, vp, i, vp, vp, vp, vp, i, i, vp, sz, vp]
@@ -182,6 +188,41 @@ def pfaffian_nopiv(A, t, ipiv, log_abs_pf, sign, block_size: int = 0, precision:
                                      work.numel(), _stream(stream))
     if st != SKLTLT_OK:
         raise SkltltError(st, "skltlt_pfaffian_nopiv")
+    return st
+
+
+def left_workspace_size(n: int, block_size: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    st = lib().skltlt_left_workspace_size(int(n), int(block_size), ctypes.byref(out))
+    if st != SKLTLT_OK:
+        raise SkltltError(st, "skltlt_left_workspace_size")
+    return int(out.value)
+
+
+def factor_left(A, t, ipiv, block_size: int = 0, work=None, stream=None):
+    """skltlt_factor_left (left-looking, no pivoting) on device tensors."""
+    n = A.shape[0]
+    lda = _lda_of(A)
+    if work is None:
+        work = alloc_workspace(left_workspace_size(n, block_size), A.device)
+    st = lib().skltlt_factor_left(n, _ptr(A), lda, _ptr(t), _ptr(ipiv), int(block_size), FP64,
+                                  _ptr(work), work.numel(), _stream(stream))
+    if st != SKLTLT_OK:
+        raise SkltltError(st, "skltlt_factor_left")
+    return st
+
+
+def pfaffian_left(A, t, ipiv, log_abs_pf, sign, block_size: int = 0, work=None, stream=None):
+    """skltlt_pfaffian_left on device tensors."""
+    n = A.shape[0]
+    lda = _lda_of(A)
+    if work is None:
+        work = alloc_workspace(left_workspace_size(n, block_size), A.device)
+    st = lib().skltlt_pfaffian_left(n, _ptr(A), lda, _ptr(t), _ptr(ipiv), _ptr(log_abs_pf),
+                                    _ptr(sign), int(block_size), FP64, _ptr(work), work.numel(),
+                                    _stream(stream))
+    if st != SKLTLT_OK:
+        raise SkltltError(st, "skltlt_pfaffian_left")
     return st
 
 

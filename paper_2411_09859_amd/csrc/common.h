@@ -80,6 +80,11 @@ void nopiv_init_attrs();
 // p[i] = i for i < n
 hipError_t launch_iota(int *p, int n, hipStream_t s);
 
+// W[i][j] += sum_k opI[i][k] opJ[j][k] for the columns c0 .. c0+nb-1 (nb <=
+// 128) and rows i > j (the left-looking panel update).
+hipError_t launch_lkupd(double *W, int ldw, int n, int c0, int nb, const double *opI,
+                        const double *opJ, int ldo, int K, hipStream_t s);
+
 // Wn[i][j] = Wc[perm[i]][perm[j]] - (U V^T - V U^T)[i][j] for i != j >= cp.
 hipError_t launch_skr2k(const double *Wc, double *Wn, int n, int cp, int nq,
                         const FactorWs &ws, int precision, hipStream_t s);

@@ -1,0 +1,128 @@
+// MFMA tile machinery shared by the trailing update (skr2k) and the
+// left-looking panel update: a 128 x 128 output tile per 256-thread
+// workgroup, four waves of 64 x 64 (each a 4 x 4 grid of 16 x 16 MFMA
+// blocks), operands streamed through a double-buffered LDS stage in K-chunks
+// of KC.  The operands are column-major with leading dimension ldo: opI
+// holds the tile's rows i (columns = k), opJ the tile's columns j.  The MFMA
+// computes the transposed tile D[j][i] += sum_k opJ[j][k] opI[i][k].
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace skl {
+
+constexpr int TM = 128;    // tile rows (i) and columns (j)
+constexpr int TMP = 144;   // padded LDS row (k-rows 1152 B apart: banks shift by 128 B)
+constexpr int KC = 16;     // K chunk staged in LDS
+
+template <typename T> struct MfmaT;
+// Output layout of the 16x16 MFMA result held by lane l (value q of 4),
+// measured on gfx950: fp64 holds rows (l/16) + 4q, fp32 rows 4(l/16) + q;
+// the column is l%16 for both.
+template <> struct MfmaT<double> {
+    typedef double __attribute__((ext_vector_type(4))) acc4;
+    static __device__ __forceinline__ acc4 mma(double a, double b, acc4 c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int lk, int q) { return lk + 4 * q; }
+};
+template <> struct MfmaT<float> {
+    typedef float __attribute__((ext_vector_type(4))) acc4;
+    static __device__ __forceinline__ acc4 mma(float a, float b, acc4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int lk, int q) { return 4 * lk + q; }
+};
+
+
+// One tile's K loop.  Every load is issued unconditionally (clamped
+// address) and masked only when the chunk is written to LDS: with a fixed
+// number of loads per chunk and no use right after them, the compiler waits
+// for the chunk that is due while the prefetched one stays in flight (loads
+// skipped by branches, or used at once, make it wait for all of them).
+template <typename T>
+struct TileK {
+    static constexpr int PER = (KC * TM) / 256; // elements per thread per operand and chunk
+    T (*sI)[KC][TMP];
+    T (*sJ)[KC][TMP];
+    const T *opI;
+    const T *opJ;
+    int ldo, n, i0, j0, K, nk, tid;
+    T ri[PER], rj[PER];
+
+    __device__ __forceinline__ TileK(T (*sI_)[KC][TMP], T (*sJ_)[KC][TMP], const T *opI_,
+                                     const T *opJ_, int ldo_, int n_, int i0_, int j0_, int K_)
+        : sI(sI_), sJ(sJ_), opI(opI_), opJ(opJ_), ldo(ldo_), n(n_), i0(i0_), j0(j0_), K(K_),
+          nk((K_ + KC - 1) / KC), tid(threadIdx.x)
+    {
+    }
+    __device__ __forceinline__ void load_chunk(int kc)
+    {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * 256;
+            const int rr = e % TM;
+            const int k = kc * KC + e / TM;
+            const int kk = (k < K) ? k : 0;
+            ri[q] = opI[(size_t)kk * ldo + min(i0 + rr, n - 1)];
+            rj[q] = opJ[(size_t)kk * ldo + min(j0 + rr, n - 1)];
+        }
+    }
+    __device__ __forceinline__ void store_chunk(int buf, int kc)
+    {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * 256;
+            const int rr = e % TM;
+            const bool kok = kc * KC + e / TM < K;
+            sI[buf][e / TM][rr] = (kok && i0 + rr < n) ? ri[q] : (T)0;
+            sJ[buf][e / TM][rr] = (kok && j0 + rr < n) ? rj[q] : (T)0;
+        }
+    }
+    // the first chunk in LDS, the second in flight
+    __device__ __forceinline__ void prologue()
+    {
+        load_chunk(0);
+        store_chunk(0, 0);
+        if (nk > 1)
+            load_chunk(1);
+        __syncthreads();
+    }
+    // acc[bi][bj] (16 x 16 block bi of this wave's rows, bj of its columns)
+    // += the product over all K; ends with a barrier
+    template <typename Acc>
+    __device__ __forceinline__ void run(Acc (&acc)[4][4], bool active, int wi, int wj, int lrow,
+                                        int lk)
+    {
+        for (int kc = 0; kc < nk; ++kc) {
+            const int cur = kc & 1;
+            if (kc + 1 < nk) {
+                store_chunk(cur ^ 1, kc + 1); // buffer freed by the barrier ending step kc-1
+                if (kc + 2 < nk)
+                    load_chunk(kc + 2); // in flight during this chunk's MFMAs
+            }
+            if (active) {
+#pragma unroll
+                for (int ks = 0; ks < KC; ks += 4) {
+                    T fa[4], fb[4];
+#pragma unroll
+                    for (int bj = 0; bj < 4; ++bj)
+                        fa[bj] = sJ[cur][ks + lk][wj * 64 + bj * 16 + lrow];
+#pragma unroll
+                    for (int bi = 0; bi < 4; ++bi)
+                        fb[bi] = sI[cur][ks + lk][wi * 64 + bi * 16 + lrow];
+#pragma unroll
+                    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                        for (int bj = 0; bj < 4; ++bj)
+                            acc[bi][bj] = MfmaT<T>::mma(fa[bj], fb[bi], acc[bi][bj]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+};
+
+}  // namespace skl

@@ -296,6 +296,153 @@ extern "C" int skltlt_pfaffian_nopiv(int n, double *A, int lda, double *t, int *
     return SKLTLT_OK;
 }
 
+// ---- left-looking (Variant 3), unpivoted ------------------------------------
+// Operand columns the left-looking update accumulates: every panel but the
+// last appends 2 * ceil((nb+1)/2) columns to each of opI and opJ.
+static size_t left_kcap(int n, int b)
+{
+    size_t k = 0;
+    for (int k0 = 0; k0 < n - 1; k0 += b) {
+        const int nb = (b < n - 1 - k0) ? b : (n - 1 - k0);
+        if (k0 + nb < n - 1)
+            k += 2 * (size_t)((nb + 1) / 2);
+    }
+    return k;
+}
+
+static int left_block(int n, int block_size)
+{
+    const int b = resolve_block(n, block_size);
+    return b < nopiv_max_block() ? b : nopiv_max_block();
+}
+
+// Workspace: the factorization's (for the requested width), then opI and
+// opJ (n x kcap fp64 each).
+static size_t left_ws_bytes(int n, int block_size, size_t *opoff)
+{
+    const int b0 = resolve_block(n, block_size);
+    const size_t base = align_up(factor_ws_layout(n, b0, nullptr, nullptr));
+    if (opoff)
+        *opoff = base;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    const size_t kc = left_kcap(n, left_block(n, block_size));
+    return base + 2 * align_up(sizeof(double) * nn * (kc > 0 ? kc : 1));
+}
+
+extern "C" int skltlt_left_workspace_size(int n, int block_size, size_t *bytes)
+{
+    if (n < 0 || block_size < 0 || !bytes)
+        return SKLTLT_EINVAL;
+    int st = check_supported(n, resolve_block(n, block_size));
+    if (st != SKLTLT_OK)
+        return st;
+    *bytes = left_ws_bytes(n, block_size, nullptr);
+    return SKLTLT_OK;
+}
+
+static int left_impl(int n, double *A, int lda, double *t, int *ipiv, int block_size,
+                     int precision, void *work, size_t work_bytes, hipStream_t s)
+{
+    if (n < 0 || lda < (n > 1 ? n : 1) || block_size < 0)
+        return SKLTLT_EINVAL;
+    if (precision != SKLTLT_FP64 && precision != SKLTLT_FP32_UPDATE)
+        return SKLTLT_EINVAL;
+    if (precision != SKLTLT_FP64)
+        return SKLTLT_ENOTSUP;
+    if (n >= 1 && (!A || !ipiv))
+        return SKLTLT_EINVAL;
+    if (n >= 2 && !t)
+        return SKLTLT_EINVAL;
+    const int b0 = resolve_block(n, block_size);
+    int st = check_supported(n, b0);
+    if (st != SKLTLT_OK)
+        return st;
+    if (n == 0)
+        return SKLTLT_OK;
+    size_t opoff = 0;
+    const size_t need = left_ws_bytes(n, block_size, &opoff);
+    if (!work || work_bytes < need || ((uintptr_t)work % kAlign) != 0)
+        return SKLTLT_EINVAL;
+    init_device_attrs();
+    FactorWs ws;
+    factor_ws_layout(n, b0, &ws, (char *)work);
+    const int b = left_block(n, block_size);
+    const size_t kcap = left_kcap(n, b);
+    double *opI = (double *)((char *)work + opoff);
+    double *opJ = opI + align_up(sizeof(double) * (size_t)n * (kcap > 0 ? kcap : 1)) / sizeof(double);
+    {
+        const int ti = tm_begin(SKLTLT_K_OTHER, s);
+        hipError_t e = launch_iota(ipiv, n, s);
+        if (e == hipSuccess)
+            e = launch_iota(ws.perm, n, s);
+        if (e == hipSuccess && n > 1)
+            e = launch_init_full(A, lda, n, ws.W[0], ws.ldw, s);
+        if (e != hipSuccess)
+            return device_error(e, "left-looking set-up");
+        tm_end(ti, s, 0.0);
+    }
+    if (n == 1)
+        return SKLTLT_OK;
+    size_t kcur = 0;
+    for (int k0 = 0; k0 < n - 1; k0 += b) {
+        const int nb = (b < n - 1 - k0) ? b : (n - 1 - k0);
+        hipError_t e = hipSuccess;
+        if (kcur > 0) {
+            // every earlier panel's update, on this panel's columns only
+            const double m = (double)(n - k0);
+            const int ti = tm_begin(SKLTLT_K_SKR2K, s);
+            e = launch_lkupd(ws.W[0], ws.ldw, n, k0, nb, opI, opJ, n, (int)kcur, s);
+            tm_end(ti, s, 2.0 * (double)kcur * (m * nb - 0.5 * nb * (nb + 1.0)));
+            if (e != hipSuccess)
+                return device_error(e, "left-looking update launch");
+        }
+        const int tp = tm_begin(SKLTLT_K_PANEL, s);
+        e = launch_nopiv_panel(A, lda, ws.W[0], n, k0, nb, t, ws, 0, s);
+        tm_end(tp, s, 0.0);
+        if (e != hipSuccess)
+            return device_error(e, "panel launch");
+        const int cp = k0 + nb;
+        if (cp < n - 1) {
+            // this panel's [U | V] and [-V | U] join the accumulated operands
+            const int nq = (nb + 1) / 2;
+            const size_t bytes = sizeof(double) * (size_t)n * (size_t)(2 * nq);
+            e = hipMemcpyAsync(opI + kcur * (size_t)n, ws.uv, bytes, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(opJ + kcur * (size_t)n, ws.uv + (size_t)(2 * nq) * n, bytes,
+                                   hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess)
+                return device_error(e, "operand copy");
+            kcur += 2 * (size_t)nq;
+        }
+    }
+    return SKLTLT_OK;
+}
+
+extern "C" int skltlt_factor_left(int n, double *A, int lda, double *t, int *ipiv, int block_size,
+                                  int precision, void *work, size_t work_bytes, void *stream)
+{
+    return left_impl(n, A, lda, t, ipiv, block_size, precision, work, work_bytes,
+                     (hipStream_t)stream);
+}
+
+extern "C" int skltlt_pfaffian_left(int n, double *A, int lda, double *t, int *ipiv,
+                                    double *log_abs_pf, int *sign, int block_size, int precision,
+                                    void *work, size_t work_bytes, void *stream)
+{
+    if (!log_abs_pf || !sign)
+        return SKLTLT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int st = left_impl(n, A, lda, t, ipiv, block_size, precision, work, work_bytes, s);
+    if (st != SKLTLT_OK)
+        return st;
+    const int ti = tm_begin(SKLTLT_K_PFAFFIAN, s);
+    hipError_t e = launch_pfaffian(n, t, ipiv, log_abs_pf, sign, s);
+    if (e != hipSuccess)
+        return device_error(e, "pfaffian launch");
+    tm_end(ti, s, 0.0);
+    return SKLTLT_OK;
+}
+
 extern "C" int skltlt_pfaffian_partial(int n, const double *A, int lda, double *t, int *ipiv,
                                        double *log_abs_pf, int *sign, int block_size,
                                        int precision, void *work, size_t work_bytes, void *stream)

@@ -36,34 +36,11 @@
 // tiles an XCD works on at once share operand panels in its L2 (measured:
 // fewer operand re-reads, 6-10 % faster on large trailing blocks).
 #include "common.h"
+#include "mfma_tile.h"
 
 namespace skl {
 
-constexpr int TM = 128;    // tile rows (i) and columns (j)
-constexpr int TMP = 144;   // padded LDS row (k-rows 1152 B apart: banks shift by 128 B)
-constexpr int KC = 16;     // K chunk staged in LDS
 constexpr int TRS = 66;    // LDS row of the epilogue transpose (64 + 2: spreads banks)
-
-template <typename T> struct MfmaT;
-// Output layout of the 16x16 MFMA result held by lane l (value q of 4),
-// measured on gfx950: fp64 holds rows (l/16) + 4q, fp32 rows 4(l/16) + q;
-// the column is l%16 for both.
-template <> struct MfmaT<double> {
-    typedef double __attribute__((ext_vector_type(4))) acc4;
-    static __device__ __forceinline__ acc4 mma(double a, double b, acc4 c)
-    {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int drow(int lk, int q) { return lk + 4 * q; }
-};
-template <> struct MfmaT<float> {
-    typedef float __attribute__((ext_vector_type(4))) acc4;
-    static __device__ __forceinline__ acc4 mma(float a, float b, acc4 c)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int drow(int lk, int q) { return 4 * lk + q; }
-};
 
 template <typename T>
 __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict__ Wc,
@@ -122,44 +99,8 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict_
         return Wc + (size_t)sPj[gj - j0] * ldw + sPi[gi - i0];
     };
 
-    const T *opI = uv;                 // columns [0, K)
-    const T *opJ = uv + (size_t)K * n; // columns [K, 2K)
-    const int nk = (K + KC - 1) / KC;
-    constexpr int PER = (KC * TM) / 256; // elements per thread per operand and chunk
-    T ri[PER], rj[PER];
-
-    // Every load below is issued unconditionally (clamped address) and
-    // masked only when the chunk is written to LDS: with a fixed number of
-    // loads per chunk and no use right after them, the compiler waits for
-    // the chunk that is due while the prefetched one stays in flight (loads
-    // skipped by branches, or used at once, make it wait for all of them).
-    auto load_chunk = [&](int kc) {
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = tid + q * 256;
-            const int rr = e % TM;
-            const int k = kc * KC + e / TM;
-            const int kk = (k < K) ? k : 0;
-            ri[q] = opI[(size_t)kk * n + min(i0 + rr, n - 1)];
-            rj[q] = opJ[(size_t)kk * n + min(j0 + rr, n - 1)];
-        }
-    };
-    auto store_chunk = [&](int buf, int kc) {
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = tid + q * 256;
-            const int rr = e % TM;
-            const bool kok = kc * KC + e / TM < K;
-            sI[buf][e / TM][rr] = (kok && i0 + rr < n) ? ri[q] : (T)0;
-            sJ[buf][e / TM][rr] = (kok && j0 + rr < n) ? rj[q] : (T)0;
-        }
-    };
-
-    load_chunk(0);
-    store_chunk(0, 0);
-    if (nk > 1)
-        load_chunk(1);
-    __syncthreads();
+    TileK<T> tk(sI, sJ, uv, uv + (size_t)K * n, n, n, i0, j0, K);
+    tk.prologue();
 
     // Accumulators.  FP64: start from the (permuted) C tile; FP32: start from
     // zero and add the fp32 product to C in fp64 at the end.
@@ -182,32 +123,7 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict_
             }
         }
     }
-    for (int kc = 0; kc < nk; ++kc) {
-        const int cur = kc & 1;
-        if (kc + 1 < nk) {
-            store_chunk(cur ^ 1, kc + 1); // buffer freed by the barrier ending step kc-1
-            if (kc + 2 < nk)
-                load_chunk(kc + 2); // in flight during this chunk's MFMAs
-        }
-        if (active) {
-#pragma unroll
-            for (int ks = 0; ks < KC; ks += 4) {
-                T fa[4], fb[4];
-#pragma unroll
-                for (int bj = 0; bj < 4; ++bj)
-                    fa[bj] = sJ[cur][ks + lk][wj * 64 + bj * 16 + lrow];
-#pragma unroll
-                for (int bi = 0; bi < 4; ++bi)
-                    fb[bi] = sI[cur][ks + lk][wi * 64 + bi * 16 + lrow];
-#pragma unroll
-                for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-                    for (int bj = 0; bj < 4; ++bj)
-                        acc[bi][bj] = MfmaT<T>::mma(fa[bj], fb[bi], acc[bi][bj]);
-            }
-        }
-        __syncthreads();
-    }
+    tk.run(acc, active, wi, wj, lrow, lk);
     if (!active)
         return;
 

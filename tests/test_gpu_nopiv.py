@@ -1,7 +1,8 @@
-"""GPU parity of the unpivoted factorization (skltlt_factor_nopiv /
-skltlt_pfaffian_nopiv) against the oracle without pivoting, on matrices
-assembled from known factors (A = L0 T0 L0^T, the inputs the unpivoted
-algorithm is meant for).
+"""GPU parity of the unpivoted factorizations, right-looking
+(skltlt_factor_nopiv / skltlt_pfaffian_nopiv) and left-looking
+(skltlt_factor_left / skltlt_pfaffian_left), against the oracle without
+pivoting, on matrices assembled from known factors (A = L0 T0 L0^T, the
+inputs the unpivoted algorithms are meant for).
 
 Bar (FP64): ipiv the identity; ||t - t_oracle|| / ||t_oracle|| and
 ||L - L_oracle||_F / ||L_oracle||_F <= 1e-12; reconstruction residual
@@ -28,7 +29,10 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
 
-def run_nopiv(A_np, block_size=0, precision=binding.FP64, lda=None):
+VARIANTS = ["right", "left"]
+
+
+def run_nopiv(A_np, block_size=0, precision=binding.FP64, lda=None, variant="right"):
     import torch
     n = A_np.shape[0]
     lda = n if lda is None else lda
@@ -41,8 +45,12 @@ def run_nopiv(A_np, block_size=0, precision=binding.FP64, lda=None):
     ipiv = torch.full((max(n, 1),), -1, dtype=torch.int32, device="cuda")
     la = torch.zeros(1, dtype=torch.float64, device="cuda")
     sg = torch.full((1,), 9, dtype=torch.int32, device="cuda")
-    work = binding.alloc_workspace(binding.workspace_size(max(n, 1), block_size, precision))
-    binding.pfaffian_nopiv(Adev, t, ipiv, la, sg, block_size, precision, work)
+    if variant == "left":
+        work = binding.alloc_workspace(binding.left_workspace_size(max(n, 1), block_size))
+        binding.pfaffian_left(Adev, t, ipiv, la, sg, block_size, work)
+    else:
+        work = binding.alloc_workspace(binding.workspace_size(max(n, 1), block_size, precision))
+        binding.pfaffian_nopiv(Adev, t, ipiv, la, sg, block_size, precision, work)
     torch.cuda.synchronize()
     hbuf = np.asfortranarray(dev.cpu().numpy())
     return {"buf": hbuf, "A": np.asfortranarray(hbuf[:n, :n]),
@@ -71,17 +79,19 @@ CASES = [(2, 0), (3, 0), (5, 1), (16, 2), (17, 3), (64, 16), (65, 0), (130, 32),
          (257, 0), (300, 128), (513, 256), (1000, 0), (2048, 128), (2049, 64)]
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("n,b", CASES)
-def test_nopiv_parity(n, b):
-    note(f"[nopiv] n={n} b={b}")
+def test_nopiv_parity(n, b, variant):
+    note(f"[nopiv] {variant} n={n} b={b}")
     A, _, _ = inputs.skew_known_factor(n, 3000 + n, 2.0)
-    check(A, run_nopiv(A, block_size=b))
+    check(A, run_nopiv(A, block_size=b, variant=variant))
 
 
-def test_nopiv_padding_untouched():
-    note("[nopiv] lda > n")
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_nopiv_padding_untouched(variant):
+    note(f"[nopiv] {variant} lda > n")
     A, _, _ = inputs.skew_known_factor(300, 9, 2.0)
-    res = run_nopiv(A, block_size=64, lda=333)
+    res = run_nopiv(A, block_size=64, lda=333, variant=variant)
     check(A, res)
     assert np.all(res["buf"][300:, :] == 7.25)
 
@@ -119,10 +129,12 @@ def test_nopiv_solve():
     assert back <= 1e-13
 
 
-@pytest.mark.parametrize("n,b", [(8192, 128), (16384, 128), (16384, 64)])
-def test_nopiv_full_size_known_factors(n, b):
+@pytest.mark.parametrize("n,b,variant", [(8192, 128, "right"), (16384, 128, "right"),
+                                         (16384, 64, "right"), (8192, 128, "left"),
+                                         (16384, 128, "left")])
+def test_nopiv_full_size_known_factors(n, b, variant):
     import torch
-    note(f"[nopiv] full size n={n} b={b}")
+    note(f"[nopiv] {variant} full size n={n} b={b}")
     g = torch.Generator(device="cuda")
     g.manual_seed(n + b)
     L0 = torch.tril((torch.rand((n, n), generator=g, dtype=torch.float64, device="cuda") * 2 - 1)
@@ -140,7 +152,10 @@ def test_nopiv_full_size_known_factors(n, b):
     ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
     la = torch.zeros(1, dtype=torch.float64, device="cuda")
     sg = torch.zeros(1, dtype=torch.int32, device="cuda")
-    binding.pfaffian_nopiv(Af, t, ipiv, la, sg, b)
+    if variant == "left":
+        binding.pfaffian_left(Af, t, ipiv, la, sg, b)
+    else:
+        binding.pfaffian_nopiv(Af, t, ipiv, la, sg, b)
     torch.cuda.synchronize()
     assert torch.equal(ipiv.cpu(), torch.arange(n, dtype=torch.int32))
     et = (torch.linalg.norm(t - t0) / torch.linalg.norm(t0)).item()
@@ -154,3 +169,20 @@ def test_nopiv_full_size_known_factors(n, b):
     want_sg = int(torch.prod(torch.sign(-t0[0::2])).item())
     assert int(sg.item()) == want_sg
     assert abs(la.item() - want_la) <= TOL * max(1.0, abs(want_la))
+
+
+def test_left_rejects_fp32_update():
+    import torch
+    lib = binding.lib()
+    n = 8
+    A = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    t = torch.zeros(n - 1, dtype=torch.float64, device="cuda")
+    ip = torch.zeros(n, dtype=torch.int32, device="cuda")
+    work = binding.alloc_workspace(binding.left_workspace_size(n, 0))
+    import ctypes
+    p = lambda x: ctypes.c_void_p(x.data_ptr())  # noqa: E731
+    assert lib.skltlt_factor_left(n, p(A), n, p(t), p(ip), 0, binding.FP32_UPDATE, p(work),
+                                  work.numel(), None) == binding.SKLTLT_ENOTSUP
+    assert lib.skltlt_factor_left(n, p(A), n, p(t), p(ip), 0, 0, p(work), 64,
+                                  None) == binding.SKLTLT_EINVAL
+    torch.cuda.synchronize()
