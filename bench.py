@@ -93,8 +93,9 @@ def measured_traffic(n, b):
     v = profsum.read_summary(TRAFFIC_SUMMARY)
     if v.get("workload") != f"n={n} b={b}":
         return None, "counters were taken at another workload"
-    src = os.path.join(ROOT, v.get("source", ""))
-    if not os.path.exists(src) or profsum.sha256_of(src) != v.get("source_sha256"):
+    srcs = [os.path.join(ROOT, x.strip()) for x in v.get("source", "").split(",") if x.strip()]
+    if not srcs or not all(os.path.exists(x) for x in srcs) or \
+            profsum.sha256_of(",".join(srcs)) != v.get("source_sha256"):
         return None, "kernel source changed since the counters were taken"
     return float(v["traffic_bytes_per_launch"]), os.path.relpath(TRAFFIC_SUMMARY, ROOT)
 

@@ -13,12 +13,12 @@ Subcommands:
       csv`` run found under D (its ``*kernel_stats.csv``).
 
   traffic --fetch D1 --write D2 --calib-fetch D3 --calib-write D4 --mib M
-          --kernel REGEX --source FILE --algo-bytes B --cmd "..." --out F
+          --kernel REGEX --source FILE[,FILE...] --algo-bytes B --cmd "..." --out F
       Per-launch HBM traffic of the kernels matching REGEX from two counter
       runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by the
       factor (known bytes / counter reading) of the calibration runs, with the
-      SHA-256 of the kernel's source so a reader can tell when the figure no
-      longer describes the kernel.  The output is ``key: value`` text.
+      SHA-256 of the kernel's source files (concatenated, in the order given)
+      so a reader can tell when the figure no longer describes the kernel.  The output is ``key: value`` text.
 """
 from __future__ import annotations
 
@@ -58,9 +58,13 @@ def counter_per_dispatch(d, counter, kernel_re):
     return out
 
 
-def sha256_of(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def sha256_of(paths):
+    """SHA-256 of the files (a path, or comma-separated paths) concatenated."""
+    h = hashlib.sha256()
+    for path in str(paths).split(","):
+        with open(path.strip(), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def read_summary(path):
