@@ -194,7 +194,8 @@ def bench_batched(torch, binding, inputs, count, seed=4, reps=3):
 def bench_serving(torch, count, seed=5):
     """Serving stream: n log-uniform over even values in [32, 2048], FP64 /
     FP32-update tags, 64 GB budget.  A closed-loop run (all requests at t=0)
-    measures capacity; a Poisson run at 80% of it measures latency."""
+    measures capacity; Poisson runs at 50 %, 80 % and 95 % of it measure
+    latency under load."""
     from paper_2411_09859_amd.serving import GpuExecutor, Server, make_requests, summarize
     reqs = make_requests(count, seed, rate_per_s=1.0)
     for r in reqs:
@@ -206,17 +207,20 @@ def bench_serving(torch, count, seed=5):
     closed = summarize(res, wall)
     cap = closed["solves_per_s"]
     log(f"[bench] serving closed loop {closed}")
-    rate = 0.8 * cap
-    reqs = make_requests(count, seed + 1, rate_per_s=rate)
-    srv = Server(GpuExecutor(n_streams=4), budget_bytes=64 << 30)
-    t0 = time.perf_counter()
-    res = srv.run(reqs, time_limit_s=600)
-    wall = time.perf_counter() - t0
-    openl = summarize(res, wall)
-    log(f"[bench] serving poisson {openl}")
-    return {"workload": f"{count} requests (of the 100000-request stream), n log-uniform even in "
-                        f"[32,2048], FP64/FP32-update 50/50, Poisson arrivals, 64 GB budget",
-            "closed_loop": closed, "poisson_at_80pct": dict(openl, rate_per_s=rate)}
+    out = {"workload": f"{count} requests (of the 100000-request stream), n log-uniform even in "
+                       f"[32,2048], FP64/FP32-update 50/50, Poisson arrivals, 64 GB budget",
+           "closed_loop": closed}
+    for pct, sd in ((80, seed + 1), (50, seed + 2), (95, seed + 3)):
+        rate = pct / 100.0 * cap
+        reqs = make_requests(count, sd, rate_per_s=rate)
+        srv = Server(GpuExecutor(n_streams=4), budget_bytes=64 << 30)
+        t0 = time.perf_counter()
+        res = srv.run(reqs, time_limit_s=600)
+        wall = time.perf_counter() - t0
+        openl = summarize(res, wall)
+        log(f"[bench] serving poisson at {pct}% {openl}")
+        out[f"poisson_at_{pct}pct"] = dict(openl, rate_per_s=rate)
+    return out
 
 
 def main():
@@ -534,6 +538,8 @@ def main():
                                f"N(0,1)*10^U(-6,6), seed {args.seed}, FP64",
                    "n": n, "block_size": b},
         "roofline": roof,
+        "step_ms": {"mean": ms, "median": float(np.median(step_ms)), "min": float(np.min(step_ms)),
+                    "max": float(np.max(step_ms))},
         "panel": panel,
         "solve": solve,
         "pfaffian_partial": partial,
