@@ -251,8 +251,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(a single factorization is sharded by nothing here); run with --gpus 1",
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(a single factorization is not sharded); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

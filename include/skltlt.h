@@ -54,7 +54,7 @@ typedef enum {
     SKLTLT_EINVAL = -1,  /* bad argument (size, pointer, workspace, enum)    */
     SKLTLT_ENOMEM = -2,  /* reserved: the library itself never allocates     */
     SKLTLT_EDEVICE = -3, /* a HIP call or kernel launch failed               */
-    SKLTLT_ENOTSUP = -4  /* size or option outside what this build supports  */
+    SKLTLT_ENOTSUP = -4  /* size or option outside what the library supports */
 } skltlt_status;
 
 typedef enum {
