@@ -185,10 +185,10 @@ int skltlt_batched_workspace_size(int batch, size_t *bytes);
 /* Many independent small factorizations and Pfaffians in one persistent
  * kernel launch: each workgroup takes the next matrix from a queue and runs
  * the fused blocked algorithm of Sec. 3.6.3 on it with a small block size
- * (the two-step case b = 2 is Sec. 3.5.2), keeping the trailing matrix in
- * the workgroup's LDS when it fits.  No host synchronization, no host
- * staging: all descriptors are device arrays, so the call can be captured
- * in a hipGraph.
+ * (the two-step case b = 2 is Sec. 3.5.2), the panel's rows of L in the
+ * workgroup's LDS and the trailing matrix in the caller's buffer.  No host
+ * synchronization, no host staging: all descriptors are device arrays, so
+ * the call can be captured in a hipGraph.
  *   batch        number of matrices (>= 0).
  *   n (device)   batch orders, each in [0, max_n].
  *   A (device)   batch device pointers, each to an n[i] x n[i] matrix with
@@ -201,7 +201,8 @@ int skltlt_batched_workspace_size(int batch, size_t *bytes);
  *                (n[i] < 0, n[i] > max_n or lda[i] < max(1, n[i])); a
  *                rejected entry's buffers are not touched.
  *   max_n (host) upper bound of the n[i], at most skltlt_batched_max_n().
- *   block_size   0 = the autotuned choice for max_n, else the panel width.
+ *   block_size   0 = the autotuned choice for each n[i], else the panel
+ *                width, at most 32 (SKLTLT_ENOTSUP above).
  *   precision    SKLTLT_FP64 (SKLTLT_FP32_UPDATE returns SKLTLT_ENOTSUP).
  *   work (device), work_bytes: skltlt_batched_workspace_size bytes.
  * Each matrix's result depends only on that matrix and on (max_n,

@@ -27,7 +27,7 @@
 namespace skl {
 
 constexpr int kBT = 256;     // threads per workgroup = largest order
-constexpr int kBMaxBs = 16;  // largest panel width (2 workgroups per CU)
+constexpr int kBMaxBs = 32;  // largest panel width (2 workgroups per CU)
 constexpr int kBLd = kBMaxBs + 2;
 
 __device__ __forceinline__ bool beats_b(double av, int ai, double bv, int bi)
@@ -47,24 +47,28 @@ __device__ __host__ inline int batched_bs_for(int n)
 
 struct BatchShared {
     double Lp[kBT][kBLd]; // panel rows of L, rows indexed by trailing row
-    double U[kBT][kBMaxBs / 2 + 1];
-    double V[kBT][kBMaxBs / 2 + 1];
-    double hrow[kBLd];
     double hv[kBLd];
     double tl[kBT];
     int pv[kBT];
     int gmap[kBT];
     double red_v[kBT / 64];
     int red_i[kBT / 64];
-    double bc_tau, bc_xr;
-    int bc_p;
+    double bc_xr;
     int bc_idx;
     double rsum[kBT / 64];
     int rneg[kBT / 64], rzero[kBT / 64];
 };
 
-__device__ void factor_one(BatchShared &sh, double *__restrict__ A, int lda, int n,
-                           double *__restrict__ t, int *__restrict__ ipiv, int bs)
+// The per-matrix pointers arrive through arrays, so the compiler cannot tell
+// that they point to device memory: generic (flat) accesses also count
+// against the LDS wait counter, and every wait for an LDS result would then
+// wait for the outstanding matrix accesses too.  factor_one takes them in
+// the global address space.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) int gint;
+
+__device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, int n,
+                           gdouble *__restrict__ t, gint *__restrict__ ipiv, int bs)
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -86,8 +90,9 @@ __device__ void factor_one(BatchShared &sh, double *__restrict__ A, int lda, int
             const double carried = (k0 == 0) ? 0.0 : sh.Lp[i][kBLd - 1];
             sh.Lp[i][0] = carried;
         }
+        // h of the first step is zero (column 0 has no earlier panel column)
         for (int a = tid; a < kBLd; a += kBT)
-            sh.hrow[a] = 0.0;
+            sh.hv[a] = 0.0;
         double ycol = valid ? A[(size_t)k0 * lda + i] : 0.0;
         __syncthreads();
 
@@ -95,17 +100,8 @@ __device__ void factor_one(BatchShared &sh, double *__restrict__ A, int lda, int
             const int c = k0 + j;
             const int r = c + 1;
             const bool last = (r == k0 + nb);
-            // h = T_p L[c, panel]^T (L[c][j] = 1)
-            if (tid <= j) {
-                const int a = tid;
-                double v = 0.0;
-                if (a + 1 <= j)
-                    v -= sh.tl[k0 + a] * ((a + 1 < j) ? sh.hrow[a + 1] : 1.0);
-                if (a >= 1)
-                    v += sh.tl[k0 + a - 1] * sh.hrow[a - 1];
-                sh.hv[a] = v;
-            }
-            __syncthreads();
+            // x = Y[., c] - L_p h, h = T_p L[c, panel]^T formed in the
+            // previous step (zero at j = 0)
             const bool cand = valid && (i >= r);
             double x = 0.0;
             if (cand) {
@@ -114,7 +110,9 @@ __device__ void factor_one(BatchShared &sh, double *__restrict__ A, int lda, int
                     s += sh.Lp[i][a] * sh.hv[a];
                 x = ycol - s;
             }
-            // argmax over the workgroup (first index on ties)
+            // argmax over the workgroup (first index on ties): per wave by
+            // shuffles, then every thread reduces the wave results in the
+            // same order (no serial step, no extra barrier)
             double cv = cand ? x : 0.0;
             int ci = cand ? i : INT_MAX;
             for (int off = 32; off >= 1; off >>= 1) {
@@ -130,30 +128,35 @@ __device__ void factor_one(BatchShared &sh, double *__restrict__ A, int lda, int
                 sh.red_i[wave] = ci;
             }
             __syncthreads();
-            if (tid == 0) {
-                double bv = sh.red_v[0];
-                int bi = sh.red_i[0];
-                for (int q = 1; q < kBT / 64; ++q)
-                    if (beats_b(sh.red_v[q], sh.red_i[q], bv, bi)) {
-                        bv = sh.red_v[q];
-                        bi = sh.red_i[q];
-                    }
-                if (bi < r || bi >= n) { // cannot happen: row r is a candidate
-                    bi = r;
-                    bv = __longlong_as_double(0x7ff8000000000000ll);
+            double tau = sh.red_v[0];
+            int p = sh.red_i[0];
+#pragma unroll
+            for (int q = 1; q < kBT / 64; ++q)
+                if (beats_b(sh.red_v[q], sh.red_i[q], tau, p)) {
+                    tau = sh.red_v[q];
+                    p = sh.red_i[q];
                 }
-                sh.bc_tau = bv;
-                sh.bc_p = bi;
-                sh.tl[c] = bv;
-                sh.pv[r] = bi;
+            if (p < r || p >= n) { // cannot happen: row r is a candidate
+                p = r;
+                tau = __longlong_as_double(0x7ff8000000000000ll);
             }
-            __syncthreads();
-            const int p = sh.bc_p;
-            const double tau = sh.bc_tau;
-            // pivot row of L for the next step's h (row p before the
-            // exchange); row r hands its x to row p
-            if (tid <= j)
-                sh.hrow[tid] = sh.Lp[p][tid];
+            if (tid == 0) {
+                sh.tl[c] = tau;
+                sh.pv[r] = p;
+            }
+            // h of the next step from the pivot row of L (row p before the
+            // exchange, entry j+1 the unit diagonal) and t; hv is no longer
+            // read in this step
+            if (tid <= j + 1 && j + 1 < nb) {
+                const int a = tid;
+                double v = 0.0;
+                if (a <= j)
+                    v -= ((a == j) ? tau : sh.tl[k0 + a]) * ((a < j) ? sh.Lp[p][a + 1] : 1.0);
+                if (a >= 1)
+                    v += ((a - 1 == j) ? tau : sh.tl[k0 + a - 1]) * sh.Lp[p][a - 1];
+                sh.hv[a] = v;
+            }
+            // row r hands its x to row p
             if (i == r)
                 sh.bc_xr = x;
             __syncthreads();
@@ -168,12 +171,12 @@ __device__ void factor_one(BatchShared &sh, double *__restrict__ A, int lda, int
             // symmetric exchange r <-> p of the trailing matrix (lower
             // storage), then ycol = Y'[i, r]
             if (valid && i > r) {
-                double *colr = A + (size_t)r * lda;
+                gdouble *colr = A + (size_t)r * lda;
                 double ynew;
                 if (p == r) {
                     ynew = colr[i];
                 } else if (i > p) {
-                    double *colp = A + (size_t)p * lda;
+                    gdouble *colp = A + (size_t)p * lda;
                     const double av = colr[i];
                     const double bv = colp[i];
                     colp[i] = av;
@@ -181,7 +184,7 @@ __device__ void factor_one(BatchShared &sh, double *__restrict__ A, int lda, int
                         colr[i] = bv;
                     ynew = bv;
                 } else if (i < p) {
-                    double *pi = A + (size_t)i * lda + p;
+                    gdouble *pi = A + (size_t)i * lda + p;
                     const double av = colr[i];
                     const double bv = *pi;
                     *pi = -av;
@@ -219,35 +222,52 @@ __device__ void factor_one(BatchShared &sh, double *__restrict__ A, int lda, int
             t[k0 + tid] = sh.tl[k0 + tid];
             ipiv[k0 + tid + 1] = sh.pv[k0 + tid + 1];
         }
+        // U = W[:, odd] replaces the even columns of the row's L in place
+        // (column 2q is read for the last time by U_q, column nb, the
+        // carried one, is never overwritten); V = L[:, odd] stays in the odd
+        // columns.
         const int nq = (nb + 1) / 2;
         if (valid && i >= cp) {
             for (int q = 0; q < nq; ++q) {
                 double u = -sh.tl[k0 + 2 * q] * sh.Lp[i][2 * q];
                 if (2 * q + 2 <= nb)
                     u += sh.tl[k0 + 2 * q + 1] * sh.Lp[i][2 * q + 2];
-                sh.U[i][q] = u;
-                sh.V[i][q] = sh.Lp[i][2 * q + 1];
+                sh.Lp[i][2 * q] = u;
             }
         }
         __syncthreads();
-        // C -= U V^T - V U^T on the strict lower triangle of rows/cols >= cp
+        // C -= U V^T - V U^T on the strict lower triangle of rows/cols >= cp.
+        // Thread ii updates its row; the columns go in groups of kUpd whose
+        // loads are all issued before any of them is used (one column at a
+        // time, every column waited for its own round trip to L2).
         if (cp < n - 1) {
-            for (int jj = cp; jj < n - 1; ++jj) {
-                double uj[kBMaxBs / 2 + 1], vj[kBMaxBs / 2 + 1];
+            constexpr int kUpd = 16;
+            constexpr int kQ = kBMaxBs / 2 + 1;
+            const int ii = tid;
+            double ui[kQ], vi[kQ];
 #pragma unroll
-                for (int q = 0; q < kBMaxBs / 2 + 1; ++q) {
-                    uj[q] = (q < nq) ? sh.U[jj][q] : 0.0;
-                    vj[q] = (q < nq) ? sh.V[jj][q] : 0.0;
+            for (int q = 0; q < kQ; ++q) {
+                ui[q] = (q < nq && ii < n) ? sh.Lp[ii][2 * q] : 0.0;
+                vi[q] = (q < nq && ii < n) ? sh.Lp[ii][2 * q + 1] : 0.0;
+            }
+            for (int j0 = cp; j0 < n - 1; j0 += kUpd) {
+                double cv[kUpd];
+#pragma unroll
+                for (int u = 0; u < kUpd; ++u) {
+                    const int jj = j0 + u;
+                    cv[u] = (jj < n - 1 && ii > jj && ii < n) ? A[(size_t)jj * lda + ii] : 0.0;
                 }
-                const int ii = tid;
-                if (ii > jj && ii < n) {
-                    double acc = 0.0;
 #pragma unroll
-                    for (int q = 0; q < kBMaxBs / 2 + 1; ++q)
-                        if (q < nq)
-                            acc += sh.U[ii][q] * vj[q] - sh.V[ii][q] * uj[q];
-                    double *cptr = A + (size_t)jj * lda + ii;
-                    *cptr -= acc;
+                for (int u = 0; u < kUpd; ++u) {
+                    const int jj = j0 + u;
+                    if (jj < n - 1 && ii > jj && ii < n) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int q = 0; q < kQ; ++q)
+                            if (q < nq)
+                                acc += ui[q] * sh.Lp[jj][2 * q + 1] - vi[q] * sh.Lp[jj][2 * q];
+                        A[(size_t)jj * lda + ii] = cv[u] - acc;
+                    }
                 }
             }
         }
@@ -267,18 +287,26 @@ __device__ void factor_one(BatchShared &sh, double *__restrict__ A, int lda, int
     for (int B = nblk - 1; B >= 0; --B) {
         const int s = min((B + 1) * bs, nsteps); // first later step
         if (B < nblk - 1) {
-            for (int j = max(1, B * bs); j < min((B + 1) * bs, n - 1); ++j) {
-                const int col = j - 1;
-                double v = 0.0;
-                const int i = tid;
-                const bool mv = (i > s) && (i < n);
-                if (mv)
-                    v = A[(size_t)col * lda + sh.gmap[i]];
-                __syncthreads();
-                if (mv)
-                    A[(size_t)col * lda + i] = v;
-                __syncthreads();
+            // all columns of the block at once (bs <= kBMaxBs): every load
+            // is issued before the barrier, every store after it
+            const int jlo = max(1, B * bs), jhi = min((B + 1) * bs, n - 1);
+            const int i = tid;
+            const bool mv = (i > s) && (i < n);
+            const int src = mv ? sh.gmap[i] : 0;
+            double v[kBMaxBs];
+#pragma unroll
+            for (int u = 0; u < kBMaxBs; ++u) {
+                const int j = jlo + u;
+                v[u] = (mv && j < jhi) ? A[(size_t)(j - 1) * lda + src] : 0.0;
             }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kBMaxBs; ++u) {
+                const int j = jlo + u;
+                if (mv && j < jhi)
+                    A[(size_t)(j - 1) * lda + i] = v[u];
+            }
+            __syncthreads();
         }
         // g := (transpositions of block B, last step innermost) o g
         const int lo = B * bs;
@@ -386,7 +414,7 @@ __global__ __launch_bounds__(kBT) void batched_kernel(int batch, const int *__re
             sh.pv[q] = q;
         }
         __syncthreads();
-        factor_one(sh, Av[idx], lda, n, tv[idx], ipv[idx], bs);
+        factor_one(sh, (gdouble *)Av[idx], lda, n, (gdouble *)tv[idx], (gint *)ipv[idx], bs);
         __syncthreads();
         if (log_abs_pf && sign)
             pfaffian_one(sh, n, &log_abs_pf[idx], &sign[idx]);

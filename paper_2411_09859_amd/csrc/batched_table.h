@@ -4,13 +4,13 @@
 namespace skl {
 struct BatchedTune { int n_max; int bs; };
 constexpr BatchedTune kBatchedTune[] = {
-    {32, 16},
-    {64, 16},
-    {96, 16},
-    {128, 16},
-    {160, 16},
-    {192, 16},
-    {224, 16},
-    {256, 16},
+    {32, 32},
+    {64, 32},
+    {96, 32},
+    {128, 32},
+    {160, 32},
+    {192, 32},
+    {224, 32},
+    {256, 32},
 };
 }  // namespace skl

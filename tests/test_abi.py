@@ -85,3 +85,16 @@ def test_batched_argument_checks():
     L = _lib_or_skip()
     sz = ctypes.c_size_t(0)
     assert L.skltlt_batched_workspace_size(-1, ctypes.byref(sz)) == -1
+
+
+def test_batched_argument_checks():
+    """Argument checks of skltlt_batched run before anything is enqueued."""
+    L = _lib_or_skip()
+    # panel width above the supported 32
+    assert L.skltlt_batched(1, None, None, None, None, None, None, None, None, 16, 33, 0, None, 0,
+                            None) == binding.SKLTLT_ENOTSUP
+    # negative batch, orders above the kernel's 256
+    assert L.skltlt_batched(-1, None, None, None, None, None, None, None, None, 16, 0, 0, None, 0,
+                            None) == binding.SKLTLT_EINVAL
+    assert L.skltlt_batched(1, None, None, None, None, None, None, None, None, 257, 0, 0, None, 0,
+                            None) == binding.SKLTLT_ENOTSUP
