@@ -28,7 +28,11 @@ namespace skl {
 
 constexpr int kBT = 256;     // threads per workgroup = largest order
 constexpr int kBMaxBs = 32;  // largest panel width (2 workgroups per CU)
-constexpr int kBLd = kBMaxBs + 2;
+// LDS row of the panel's L: columns 0 .. kBMaxBs; the last slot also holds
+// the carried column between panels (moved to column 0 at the next panel's
+// start).  An odd number of doubles puts the rows read by one wave's lanes in
+// different bank pairs.
+constexpr int kBLd = kBMaxBs + 1;
 
 __device__ __forceinline__ bool beats_b(double av, int ai, double bv, int bi)
 {
