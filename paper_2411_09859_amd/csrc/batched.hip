@@ -14,12 +14,14 @@
 // (one atomic per matrix), so the whole batch is one launch with no host
 // synchronization and the launch can be captured in a hipGraph.  The
 // trailing matrix stays in the caller's buffer (L2-resident at these sizes);
-// the panel rows of L, the operands U and V and the pivots live in LDS.  The
+// the panel rows of L (for the update, U in place of their even columns, V
+// in the odd ones) and the pivots live in LDS.  The
 // arithmetic of a matrix depends only on that matrix and on bs, never on
 // which workgroup runs it or on the other matrices.
 #include "../../include/skltlt.h"
 #include "batched_table.h"
 #include "common.h"
+#include "wave_max.h"
 
 #include <climits>
 #include <cmath>
@@ -109,23 +111,39 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
             const bool cand = valid && (i >= r);
             double x = 0.0;
             if (cand) {
-                double s = 0.0;
-                for (int a = 0; a <= j; ++a)
-                    s += sh.Lp[i][a] * sh.hv[a];
-                x = ycol - s;
-            }
-            // argmax over the workgroup (first index on ties): per wave by
-            // shuffles, then every thread reduces the wave results in the
-            // same order (no serial step, no extra barrier)
-            double cv = cand ? x : 0.0;
-            int ci = cand ? i : INT_MAX;
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double ov = __shfl_xor(cv, off, 64);
-                const int oi = __shfl_xor(ci, off, 64);
-                if (beats_b(ov, oi, cv, ci)) {
-                    cv = ov;
-                    ci = oi;
+                // in blocks of 8 terms, all reads of a block issued before
+                // its products, four partial sums; entries past column j are
+                // masked (LDS there may hold anything)
+                double sp[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int a0 = 0; a0 <= j; a0 += 8) {
+                    double lv[8], hh[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        lv[u] = (a0 + u <= j) ? sh.Lp[i][a0 + u] : 0.0;
+                        hh[u] = (a0 + u <= j) ? sh.hv[a0 + u] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        sp[u & 3] += lv[u] * hh[u];
                 }
+                x = ycol - ((sp[0] + sp[1]) + (sp[2] + sp[3]));
+            }
+            // argmax over the workgroup (first index on ties).  Per wave: the
+            // largest |x| as its bit pattern (monotone for non-negative
+            // doubles) by DPP moves, then the first candidate lane holding it
+            // by a ballot (lanes are rows in order); then every thread
+            // reduces the wave results in the same order (no serial step, no
+            // extra barrier).
+            const unsigned long long key =
+                cand ? (unsigned long long)__double_as_longlong(fabs(x)) : 0ull;
+            const unsigned long long km = wave_max_u64(key);
+            const unsigned long long top = __ballot(cand && key == km);
+            double cv = 0.0;
+            int ci = INT_MAX;
+            if (top != 0) {
+                const int wl = __ffsll((long long)top) - 1;
+                cv = readlane_f64(x, wl);
+                ci = wave * 64 + wl;
             }
             if (lane == 0) {
                 sh.red_v[wave] = cv;

@@ -42,6 +42,7 @@
 // Cross-group words (slots, the mirror) are relaxed device-scope atomics:
 // coherent across XCDs without L2 write-back or invalidation.
 #include "common.h"
+#include "wave_max.h"
 
 #include <climits>
 
@@ -56,48 +57,11 @@ __device__ __forceinline__ bool beats(double av, int ai, double bv, int bi)
     return (aa > bb) | ((aa == bb) & (ai < bi));
 }
 
-__device__ __forceinline__ double readlane_f64(double v, int l)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
 // Wave-wide argmax in the pivot order; every lane receives the winner's
 // (v, idx, ph).  First the largest |v| as its bit pattern (monotone for
 // non-negative doubles, two dwords per exchange), then the lanes holding it
 // are found with a ballot; only an exact tie needs a second pass for the
 // smallest index.  Lanes without a candidate hold v = 0, idx = INT_MAX.
-// One step of a 64-bit unsigned max over lanes with a DPP data movement
-// (row_mask selects the rows that take the moved value; others keep theirs).
-template <int CTRL, int ROWS>
-__device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long x)
-{
-    const int lo = (int)(unsigned)x, hi = (int)(unsigned)(x >> 32);
-    const unsigned olo = (unsigned)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xf, false);
-    const unsigned ohi = (unsigned)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xf, false);
-    const unsigned long long o = ((unsigned long long)ohi << 32) | olo;
-    return (o > x) ? o : x;
-}
-
-// Largest value over the wave, in every lane: pairs and quads (quad_perm),
-// 8 and 16 lanes (row half mirror, row mirror), then lane 15 of each row into
-// the next and lane 31 into the upper half (row_bcast 15 / 31): lane 63 holds
-// the maximum, which is read back as a uniform value.  All VALU, no LDS.
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
-{
-    x = dpp_max_u64<0xb1, 0xf>(x);  // quad_perm [1,0,3,2]
-    x = dpp_max_u64<0x4e, 0xf>(x);  // quad_perm [2,3,0,1]
-    x = dpp_max_u64<0x141, 0xf>(x); // row_half_mirror
-    x = dpp_max_u64<0x140, 0xf>(x); // row_mirror
-    x = dpp_max_u64<0x142, 0xa>(x); // row_bcast:15 into rows 1 and 3
-    x = dpp_max_u64<0x143, 0xc>(x); // row_bcast:31 into rows 2 and 3
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, 63);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), 63);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
 __device__ __forceinline__ void wave_argmax(double &v, int &idx, int &ph)
 {
     const unsigned long long key = (unsigned long long)__double_as_longlong(fabs(v));
