@@ -258,37 +258,65 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
             }
         }
         __syncthreads();
-        // C -= U V^T - V U^T on the strict lower triangle of rows/cols >= cp.
-        // Thread ii updates its row; the columns go in groups of kUpd whose
-        // loads are all issued before any of them is used (one column at a
-        // time, every column waited for its own round trip to L2).
+        // C -= U V^T - V U^T on the strict lower triangle of rows/cols >= cp,
+        // written as C -= A B^T with K = 2 nq: A[i][k] = L'[i][k] (U_q at
+        // k = 2q, V_q at 2q + 1, the row's LDS entries as they now stand) and
+        // B[j][k] = L'[j][k + 1] for even k, -L'[j][k - 1] for odd k.  On
+        // 16 x 16 blocks with the FP64 MFMA (per 16x16x4 step a lane supplies
+        // entry k = l / 16 of row or column l % 16; the result's lane l, value
+        // q is column (l / 16) + 4q at row l % 16): a block reads 2 operand
+        // values per lane and k-step from LDS, where a thread per row read
+        // every column's operands for each of its products.  Each wave takes
+        // every fourth block, kGrp at a time, their C loads issued before the
+        // products.
         if (cp < n - 1) {
-            constexpr int kUpd = 16;
-            constexpr int kQ = kBMaxBs / 2 + 1;
-            const int ii = tid;
-            double ui[kQ], vi[kQ];
+            constexpr int kGrp = 4;
+            const int m = n - cp;
+            const int nt = (m + 15) / 16;
+            const int nblk = nt * (nt + 1) / 2;
+            const int K = 2 * nq;
+            const int lrow = lane & 15, lk = lane >> 4;
+            for (int t0 = wave; t0 < nblk; t0 += 4 * kGrp) {
+                double cv[kGrp][4];
+                int gi[kGrp], j0[kGrp];
+                bool ok[kGrp];
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                ui[q] = (q < nq && ii < n) ? sh.Lp[ii][2 * q] : 0.0;
-                vi[q] = (q < nq && ii < n) ? sh.Lp[ii][2 * q + 1] : 0.0;
-            }
-            for (int j0 = cp; j0 < n - 1; j0 += kUpd) {
-                double cv[kUpd];
+                for (int u = 0; u < kGrp; ++u) {
+                    const int tb = t0 + 4 * u;
+                    ok[u] = tb < nblk;
+                    int bI, bJ;
+                    tile_of(ok[u] ? tb : 0, &bI, &bJ);
+                    gi[u] = cp + 16 * bI + lrow;
+                    j0[u] = cp + 16 * bJ;
 #pragma unroll
-                for (int u = 0; u < kUpd; ++u) {
-                    const int jj = j0 + u;
-                    cv[u] = (jj < n - 1 && ii > jj && ii < n) ? A[(size_t)jj * lda + ii] : 0.0;
+                    for (int q = 0; q < 4; ++q) {
+                        const int gj = j0[u] + lk + 4 * q;
+                        cv[u][q] = (ok[u] && gi[u] < n && gj < gi[u])
+                                       ? A[(size_t)gj * lda + gi[u]] : 0.0;
+                    }
                 }
 #pragma unroll
-                for (int u = 0; u < kUpd; ++u) {
-                    const int jj = j0 + u;
-                    if (jj < n - 1 && ii > jj && ii < n) {
-                        double acc = 0.0;
+                for (int u = 0; u < kGrp; ++u) {
+                    typedef double __attribute__((ext_vector_type(4))) acc4;
+                    acc4 acc = {0.0, 0.0, 0.0, 0.0};
+                    const int ri = min(gi[u], n - 1);            // row side
+                    const int rj = min(j0[u] + lrow, n - 1);     // column side
+                    const bool rok = gi[u] < n, cok = j0[u] + lrow < n;
+                    for (int ks = 0; ks < K; ks += 4) {
+                        const int k = ks + lk;
+                        const bool kok = k < K;
+                        const int kb = (k & 1) ? k - 1 : k + 1;
+                        const double av = sh.Lp[ri][kok ? k : 0];
+                        const double bv = sh.Lp[rj][kok ? kb : 0];
+                        const double fb = (kok && rok) ? av : 0.0;
+                        const double fa = (kok && cok) ? ((k & 1) ? -bv : bv) : 0.0;
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb, acc, 0, 0, 0);
+                    }
 #pragma unroll
-                        for (int q = 0; q < kQ; ++q)
-                            if (q < nq)
-                                acc += ui[q] * sh.Lp[jj][2 * q + 1] - vi[q] * sh.Lp[jj][2 * q];
-                        A[(size_t)jj * lda + ii] = cv[u] - acc;
+                    for (int q = 0; q < 4; ++q) {
+                        const int gj = j0[u] + lk + 4 * q;
+                        if (ok[u] && gi[u] < n && gj < gi[u])
+                            A[(size_t)gj * lda + gi[u]] = cv[u][q] - acc[q];
                     }
                 }
             }
