@@ -178,6 +178,19 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
                     v += ((a - 1 == j) ? tau : sh.tl[k0 + a - 1]) * sh.Lp[p][a - 1];
                 sh.hv[a] = v;
             }
+            // the exchange's reads of this row's entries (their addresses are
+            // known with the pivot; every entry is read and written by one
+            // thread only): issued here, their latency overlaps the rest of
+            // the step up to the barrier
+            const bool xrow = valid && i > r;
+            double av = 0.0, bv = 0.0;
+            if (xrow) {
+                av = A[(size_t)r * lda + i];
+                if (p != r && i > p)
+                    bv = A[(size_t)p * lda + i];
+                else if (p != r && i < p)
+                    bv = A[(size_t)i * lda + p];
+            }
             // row r hands its x to row p
             if (i == r)
                 sh.bc_xr = x;
@@ -192,29 +205,22 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
                 x = sh.bc_xr;
             // symmetric exchange r <-> p of the trailing matrix (lower
             // storage), then ycol = Y'[i, r]
-            if (valid && i > r) {
+            if (xrow) {
                 gdouble *colr = A + (size_t)r * lda;
                 double ynew;
                 if (p == r) {
-                    ynew = colr[i];
+                    ynew = av;
                 } else if (i > p) {
-                    gdouble *colp = A + (size_t)p * lda;
-                    const double av = colr[i];
-                    const double bv = colp[i];
-                    colp[i] = av;
+                    A[(size_t)p * lda + i] = av;
                     if (last)
                         colr[i] = bv;
                     ynew = bv;
                 } else if (i < p) {
-                    gdouble *pi = A + (size_t)i * lda + p;
-                    const double av = colr[i];
-                    const double bv = *pi;
-                    *pi = -av;
+                    A[(size_t)i * lda + p] = -av;
                     if (last)
                         colr[i] = -bv;
                     ynew = -bv;
                 } else {
-                    const double av = colr[p];
                     if (last)
                         colr[p] = -av;
                     ynew = -av;

@@ -5,10 +5,10 @@ namespace skl {
 struct BatchedTune { int n_max; int bs; };
 constexpr BatchedTune kBatchedTune[] = {
     {32, 32},
-    {64, 32},
-    {96, 32},
-    {128, 32},
-    {160, 32},
+    {64, 24},
+    {96, 20},
+    {128, 16},
+    {160, 24},
     {192, 32},
     {224, 32},
     {256, 32},
