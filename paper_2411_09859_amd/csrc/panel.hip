@@ -510,23 +510,40 @@ __global__ __launch_bounds__(NT) void panel_kernel(
         const double tau = pv.bc_fail ? __longlong_as_double(0x7ff8000000000000ll) : pv.bc_tau;
         const int physp = pv.bc_physp;
 
-        // 5a. the pivot row of L (row p before the exchange): it is the
-        //     previous row for the next step's h.
-        //     With several groups, thread a forms h[a] of the next step from
-        //     entries a-1 and a+1 of that row (read from the mirror) and t.
-        double hn = 0.0;
+        // 5a. loads that depend on the pivot, all issued before any of them
+        //     is used (a use in between makes each wait for the one before):
+        //     - with several groups, entries a-1 and a+1 of the pivot row of
+        //       L (row p before the exchange, the previous row for the next
+        //       step's h) from the mirror, for thread a's h[a];
+        //     - the next column: entry (label i, label r) of the exchanged
+        //       matrix is Y0[orig(i), orig(r)], and orig(r) is the original
+        //       row of the register row that held p.  Every thread of a row
+        //       loads it (one address); rows that are final or absent load a
+        //       valid entry they do not use.  W is not written during the
+        //       panel.
+        //     Unused lanes read clamped addresses inside the same rows.
+        const bool hthr = multi && tid <= j + 1 && j + 1 < nb;
+        double mup = 0.0, mdn = 0.0;
         if (multi) {
-            if (tid <= j + 1 && j + 1 < nb) {
-                const int a = tid;
-                const double *mrow = mirror + (size_t)physp * ldm;
-                if (a + 1 <= j + 1) {
-                    const double up = (a + 1 < j + 1) ? ld_dev(&mrow[a + 1]) : 1.0;
-                    hn -= ((a == j) ? tau : tl[a]) * up;
-                }
-                if (a >= 1)
-                    hn += ((a - 1 == j) ? tau : tl[a - 1]) * ld_dev(&mrow[a - 1]);
+            const double *mrow = mirror + (size_t)physp * ldm;
+            mup = ld_dev(&mrow[hthr ? min(tid + 1, j + 1) : 0]);
+            mdn = ld_dev(&mrow[(hthr && tid >= 1) ? tid - 1 : 0]);
+        }
+        const double ynext = W[(size_t)(base + physp) * ldw + (exists ? orow : base)];
+
+        // 5b. the next step's h: with several groups, thread a forms h[a]
+        //     from the mirror entries and t; with one group the pivot row
+        //     copies its L row to LDS and h is formed at the next step.
+        double hn = 0.0;
+        if (hthr) {
+            const int a = tid;
+            if (a + 1 <= j + 1) {
+                const double up = (a + 1 < j + 1) ? mup : 1.0;
+                hn -= ((a == j) ? tau : tl[a]) * up;
             }
-        } else if (exists && pos == p) {
+            if (a >= 1)
+                hn += ((a - 1 == j) ? tau : tl[a - 1]) * mdn;
+        } else if (!multi && exists && pos == p) {
 #pragma unroll
             for (int q = 0; q < kNS; ++q)
                 hrow[sub + TPR * q] = Lreg[q];
@@ -535,20 +552,14 @@ __global__ __launch_bounds__(NT) void panel_kernel(
                 hrow[sub + TPR * (gr * kRing + i)] = Lnew[i];
         }
 
-        // 5b. relabel: the register row of r now holds p, the one of p holds r.
+        // 5c. relabel: the register row of r now holds p, the one of p holds r.
         if (exists) {
             if (pos == r)
                 pos = p;
             else if (pos == p)
                 pos = r;
         }
-
-        // 5c. next column: entry (label i, label r) of the exchanged matrix is
-        //     Y0[orig(i), orig(r)], and orig(r) is the original row of the
-        //     register row that held p.  W is not written during the panel.
-        if (exists && sub == 0 && pos > r)
-            ycol = W[(size_t)(base + physp) * ldw + orow];
-        ycol = __shfl(ycol, lane & ~(TPR - 1), 64);
+        ycol = ynext;
 
         // 5d. new column of L: l_i = x_i / tau for rows i > r (each register
         //     row keeps its own x); row r gets its unit diagonal.
