@@ -11,8 +11,9 @@
 //
 // One cooperative launch handles one panel of nb column steps.  A workgroup
 // of 512 threads owns R = 512/TPR consecutive trailing rows; the TPR threads
-// of a row hold that row of the panel's L (the carried column and the nb new
-// ones, column a in thread a % TPR, register a / TPR) in registers, so a
+// of a row (64/TPR lanes apart in a wave) hold that row of the panel's L (the
+// carried column and the nb new ones, column a in thread a % TPR, register
+// a / TPR) in registers, so a
 // group covers 256 rows at b = 128 and the whole n = 16384 trailing matrix
 // needs only 64 groups (the cost of the per-step exchange grows with the
 // number of groups).  Each column step c (r = c+1):
@@ -58,24 +59,31 @@ __device__ __forceinline__ bool beats(double av, int ai, double bv, int bi)
 }
 
 // Wave-wide argmax in the pivot order; every lane receives the winner's
-// (v, idx, ph).  First the largest |v| as its bit pattern (monotone for
-// non-negative doubles, two dwords per exchange), then the lanes holding it
-// are found with a ballot; only an exact tie needs a second pass for the
-// smallest index.  Lanes without a candidate hold v = 0, idx = INT_MAX.
+// (v, idx, ph).  The bit pattern of |v| orders non-negative doubles, so the
+// largest is found on its high dword first (one 32-bit DPP max); the lanes
+// holding that high dword are found with a ballot, and only when several do
+// are their low dwords compared, and only on an exact tie the indices.
+// Lanes without a candidate hold v = 0, idx = INT_MAX.
 __device__ __forceinline__ void wave_argmax(double &v, int &idx, int &ph)
 {
     const unsigned long long key = (unsigned long long)__double_as_longlong(fabs(v));
-    const unsigned long long km = wave_max_u64(key);
-    const bool top = (key == km);
+    const unsigned khi = (unsigned)(key >> 32), klo = (unsigned)key;
+    const unsigned mh = wave_max_u32(khi);
+    bool top = (khi == mh);
     unsigned long long m = __ballot(top);
     if (__popcll(m) != 1) {
-        int ci = top ? idx : INT_MAX;
+        const unsigned ml = wave_max_u32(top ? klo : 0u);
+        top = top && (klo == ml);
+        m = __ballot(top);
+        if (__popcll(m) != 1) {
+            int ci = top ? idx : INT_MAX;
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const int o = __shfl_xor(ci, off, 64);
-            ci = (o < ci) ? o : ci;
+            for (int off = 32; off >= 1; off >>= 1) {
+                const int o = __shfl_xor(ci, off, 64);
+                ci = (o < ci) ? o : ci;
+            }
+            m = __ballot(top && idx == ci);
         }
-        m = __ballot(top && idx == ci);
     }
     const int wl = __ffsll((long long)m) - 1;
     v = readlane_f64(v, wl);
@@ -178,9 +186,6 @@ struct PivotLds {
     int red_i[NW], red_ph[NW];
     double bc_tau;
     int bc_p, bc_physp, bc_fail;
-    double hand_v; // wave 1 -> wave 0 handoff of polled candidates
-    int hand_i, hand_ph;
-    unsigned hand_flag;
 };
 
 // Reduces the per-wave candidates (waves without one hold v = 0,
@@ -263,15 +268,49 @@ __device__ __forceinline__ void find_pivot(PivotLds<NT / 64> &pl, const SlotIO &
 
     // several groups: poll all slots and reduce them identically in every
     // group
-    if (multi) {
+    if (multi && G <= 128) {
+        // wave 0 alone: lane l polls slots l and l + 64 (both loads issued
+        // in every round; lanes past G read slot 0 and ignore it), then one
+        // wave argmax gives the pivot
+        if (wave == 0) {
+            const int q0 = lane, q1 = lane + 64;
+            const bool use0 = q0 < G, use1 = q1 < G;
+            const int sb = par * kSlotsPerParity;
+            u32x4 d0, d1;
+            long spins = 0;
+            for (;;) {
+                // compiler-only fence: the slot loads are ordinary
+                // intrinsics and would otherwise be hoisted out of the spin
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                d0 = sio.load(sb + (use0 ? q0 : 0));
+                d1 = sio.load(sb + (use1 ? q1 : 0));
+                const bool ok = (!use0 || SlotIO::ready(d0, stamp)) &&
+                                (!use1 || SlotIO::ready(d1, stamp));
+                if (ok)
+                    break;
+                if (pl.bc_fail || ++spins > kSpinLimit) {
+                    pl.bc_fail = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            double gv = 0.0;
+            int gi = INT_MAX, gph = 0;
+            if (use0)
+                sio.fold(d0, gv, gi, gph);
+            if (use1)
+                sio.fold(d1, gv, gi, gph);
+            wave_argmax(gv, gi, gph);
+            if (lane == 0)
+                set_pivot<NW>(pl, gv, gi, gph, r_cur, n, G, R, sio.base);
+        }
+    } else if (multi) {
         double gv = 0.0;
         int gi = INT_MAX, gph = 0;
         for (int q = tid; q < G; q += NT) {
             u32x4 d;
             long spins = 0;
             for (;;) {
-                // compiler-only fence: the slot load is an ordinary
-                // intrinsic and would otherwise be hoisted out of the spin
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
                 d = sio.load(par * kSlotsPerParity + q);
                 if (SlotIO::ready(d, stamp))
@@ -284,42 +323,7 @@ __device__ __forceinline__ void find_pivot(PivotLds<NT / 64> &pl, const SlotIO &
             }
             sio.fold(d, gv, gi, gph);
         }
-        if (G <= 128) {
-            // every candidate is in waves 0 and 1: wave 1 hands its result
-            // to wave 0 through LDS (no barrier), wave 0 broadcasts the pivot
-            if (wave == 1 && G > 64) {
-                wave_argmax(gv, gi, gph);
-                if (lane == 0) {
-                    pl.hand_v = gv;
-                    pl.hand_i = gi;
-                    pl.hand_ph = gph;
-                    __hip_atomic_store(&pl.hand_flag, stamp, __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-            } else if (wave == 0) {
-                wave_argmax(gv, gi, gph);
-                if (lane == 0) {
-                    if (G > 64) {
-                        long hs = 0;
-                        while (__hip_atomic_load(&pl.hand_flag, __ATOMIC_ACQUIRE,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP) != stamp) {
-                            if (++hs > kSpinLimit) {
-                                pl.bc_fail = 1;
-                                break;
-                            }
-                            __builtin_amdgcn_s_sleep(1);
-                        }
-                        const double hv2 = pl.hand_v;
-                        const int hi2 = pl.hand_i, hph2 = pl.hand_ph;
-                        const bool wn = beats(hv2, hi2, gv, gi);
-                        gv = wn ? hv2 : gv;
-                        gi = wn ? hi2 : gi;
-                        gph = wn ? hph2 : gph;
-                    }
-                    set_pivot<NW>(pl, gv, gi, gph, r_cur, n, G, R, sio.base);
-                }
-            }
-        } else {
+        {
             if (wave * 64 < G)
                 wave_argmax(gv, gi, gph);
             __syncthreads(); // red_* of the group argmax were consumed by thread 0
@@ -341,6 +345,27 @@ __device__ __forceinline__ void find_pivot(PivotLds<NT / 64> &pl, const SlotIO &
 }
 
 
+// Lane I of each 16-lane row of the wave, in every lane of that row (one
+// 64-bit DPP move).
+template <int I>
+__device__ __forceinline__ double row_bcast(double h)
+{
+    // every lane's source lane exists (all lanes active), so no old value
+    return __longlong_as_double(
+        __builtin_amdgcn_mov_dpp(__double_as_longlong(h), 0x150 + I, 0xf, 0xf, false));
+}
+
+// acc[i & 3] += Lr[Q0 + i] * h[i] for the slots i < N of one 16-slot block,
+// h[i] being lane i of the row of hb.
+template <int I, int N, int Q0, int LEN>
+__device__ __forceinline__ void bcast_fma(double (&acc)[4], const double (&Lr)[LEN], double hb)
+{
+    if constexpr (I < N && Q0 + I < LEN) {
+        acc[I & 3] += Lr[Q0 + I] * row_bcast<I>(hb);
+        bcast_fma<I + 1, N, Q0, LEN>(acc, Lr, hb);
+    }
+}
+
 template <int NT, int TPR, int kNS>
 __global__ __launch_bounds__(NT) void panel_kernel(
     double *__restrict__ A, int lda, const double *__restrict__ W, int ldw, int n, int k0,
@@ -357,9 +382,13 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     constexpr int kRing = 8;
     constexpr int kNSR = ((kNS + kRing - 1) / kRing) * kRing;
     constexpr int NA = kNSR * TPR; // columns addressable through the ring
+    // h is read in blocks of 16 slots (one LDS read per lane and block)
+    constexpr int kNSB = ((kNS + 15) / 16) * 16;
+    constexpr int NH = (kNSB > kNSR ? kNSB : kNSR) * TPR;
+    static_assert(TPR == 1 || TPR == 2 || TPR == 4, "a 16-lane row must hold one column class");
     extern __shared__ double stage[]; // R x 34, epilogue only
 
-    __shared__ double hv[NA];
+    __shared__ double hv[NH];
     __shared__ double hrow[NA];
     __shared__ double tl[kMaxBlock];
     __shared__ int pl[kMaxBlock];
@@ -381,8 +410,11 @@ __global__ __launch_bounds__(NT) void panel_kernel(
         w >>= 3;
     }
     const int base = k0 + 1;        // first trailing row
-    const int lr = tid / TPR;       // register row of this thread
-    const int sub = tid - lr * TPR; // column class of this thread
+    // The TPR threads of a row are RL = 64 / TPR lanes apart, so each 16-lane
+    // row of a wave holds one column class and h is broadcast inside it.
+    constexpr int RL = 64 / TPR;
+    const int lr = (tid >> 6) * RL + lane % RL; // register row of this thread
+    const int sub = lane / RL;                  // column class of this thread
     const int phys = w * R + lr;    // its row in the mirror (fixed)
     const int orow = base + phys;   // its row of the panel-start matrix (fixed)
     const bool multi = (G > 1);
@@ -416,21 +448,20 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     // ---- panel start: carried column (column 0 of the panel) and the first
     //      column of Y
     double ycol = 0.0;
-    for (int a = tid; a < NA; a += NT) {
+    for (int a = tid; a < NH; a += NT)
         hv[a] = 0.0;
+    for (int a = tid; a < NA; a += NT)
         hrow[a] = 0.0;
-    }
     if (exists && sub == 0) {
         const double l0 = (k0 == 0) ? 0.0 : lcar[pos];
         Lnew[0] = l0;
         if (multi)
             st_xcd(&mirror[(size_t)phys * ldm], l0, local);
-        ycol = W[(size_t)k0 * ldw + orow];
     }
-    ycol = __shfl(ycol, lane & ~(TPR - 1), 64);
+    if (exists) // every thread of the row (one address)
+        ycol = W[(size_t)k0 * ldw + orow];
     if (tid == 0) {
         pv.bc_fail = 0;
-        pv.hand_flag = 0u;
     }
     __syncthreads();
     const SlotIO sio(slots, base, local);
@@ -462,35 +493,38 @@ __global__ __launch_bounds__(NT) void panel_kernel(
         //    flushed ring groups from Lreg, the current group from the ring.
         const int gr = (j / TPR) / kRing; // ring group of column j (uniform)
         const bool cand = exists && (pos >= r);
-        // h is read in blocks of kHB slots, all reads of a block issued
-        // before its products (slots of the unflushed group in Lreg are 0).
-        constexpr int kHB = 16;
+        // h is read from LDS once per lane and block of 16 slots (lane i of
+        //   a 16-lane row reads slot i of the block for the row's column
+        //   class) and each slot's value is broadcast inside the row by DPP;
+        //   all reads are issued before the products.  Slots of the
+        //   unflushed group in Lreg are 0.
+        const int hl = lane & 15;
+        double hb[kNSB / 16];
+#pragma unroll
+        for (int k = 0; k < kNSB / 16; ++k)
+            hb[k] = (16 * k < gr * kRing) ? hv[sub + TPR * (16 * k + hl)] : 0.0; // uniform
+        const double hr = hv[sub + TPR * (gr * kRing + (lane & 7))];
         double sacc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int qb = 0; qb < kNS; qb += kHB) {
-            if (qb < gr * kRing) { // uniform
-                double hh[kHB];
-#pragma unroll
-                for (int i = 0; i < kHB; ++i)
-                    hh[i] = (qb + i < kNS) ? hv[sub + TPR * (qb + i)] : 0.0;
-#pragma unroll
-                for (int i = 0; i < kHB; ++i)
-                    if (qb + i < kNS)
-                        sacc[i & 3] += Lreg[qb + i] * hh[i];
-            }
-        }
-        {
-            double hh[kRing];
-#pragma unroll
-            for (int i = 0; i < kRing; ++i)
-                hh[i] = hv[sub + TPR * (gr * kRing + i)];
-#pragma unroll
-            for (int i = 0; i < kRing; ++i)
-                sacc[i & 3] += Lnew[i] * hh[i];
-        }
+        if (0 < gr * kRing)
+            bcast_fma<0, 16, 0, kNS>(sacc, Lreg, hb[0]);
+        if constexpr (kNSB > 16)
+            if (16 < gr * kRing)
+                bcast_fma<0, 16, 16, kNS>(sacc, Lreg, hb[1 % (kNSB / 16)]);
+        if constexpr (kNSB > 32)
+            if (32 < gr * kRing)
+                bcast_fma<0, 16, 32, kNS>(sacc, Lreg, hb[2 % (kNSB / 16)]);
+        if constexpr (kNSB > 48)
+            if (48 < gr * kRing)
+                bcast_fma<0, 16, 48, kNS>(sacc, Lreg, hb[3 % (kNSB / 16)]);
+        if constexpr (kNSB > 64)
+            if (64 < gr * kRing)
+                bcast_fma<0, 16, 64, kNS>(sacc, Lreg, hb[4 % (kNSB / 16)]);
+        static_assert(kNSB <= 80, "h blocks");
+        bcast_fma<0, kRing, 0, kRing>(sacc, Lnew, hr);
         double s = (sacc[0] + sacc[1]) + (sacc[2] + sacc[3]);
+        // the TPR partial sums of a row (lanes RL apart)
 #pragma unroll
-        for (int off = TPR >> 1; off >= 1; off >>= 1)
+        for (int off = 32; off >= RL; off >>= 1)
             s += __shfl_xor(s, off, 64);
         const double xv = ycol - s;
 
@@ -531,19 +565,9 @@ __global__ __launch_bounds__(NT) void panel_kernel(
         }
         const double ynext = W[(size_t)(base + physp) * ldw + (exists ? orow : base)];
 
-        // 5b. the next step's h: with several groups, thread a forms h[a]
-        //     from the mirror entries and t; with one group the pivot row
-        //     copies its L row to LDS and h is formed at the next step.
-        double hn = 0.0;
-        if (hthr) {
-            const int a = tid;
-            if (a + 1 <= j + 1) {
-                const double up = (a + 1 < j + 1) ? mup : 1.0;
-                hn -= ((a == j) ? tau : tl[a]) * up;
-            }
-            if (a >= 1)
-                hn += ((a - 1 == j) ? tau : tl[a - 1]) * mdn;
-        } else if (!multi && exists && pos == p) {
+        // 5b. with one group the pivot row copies its L row to LDS (row p
+        //     before the exchange); h is formed from it at the next step.
+        if (!multi && exists && pos == p) {
 #pragma unroll
             for (int q = 0; q < kNS; ++q)
                 hrow[sub + TPR * q] = Lreg[q];
@@ -559,12 +583,14 @@ __global__ __launch_bounds__(NT) void panel_kernel(
             else if (pos == p)
                 pos = r;
         }
-        ycol = ynext;
 
         // 5d. new column of L: l_i = x_i / tau for rows i > r (each register
         //     row keeps its own x); row r gets its unit diagonal.
         //     Column j+1 sits in ring group (j+1)/TPR/kRing; when that is a
         //     new group, the finished one is flushed first (every thread).
+        //     Its mirror store is issued while the loads above are in
+        //     flight, so it has completed sooner when the next step's
+        //     publication waits for it.
         const int a1 = j + 1;
         if (((a1 / TPR) / kRing) != gr)
             flush_ring(gr);
@@ -581,6 +607,20 @@ __global__ __launch_bounds__(NT) void panel_kernel(
                     st_xcd(&mirror[(size_t)phys * ldm + a1], l, local);
             }
         }
+
+        // 5e. with several groups, thread a forms h[a] of the next step from
+        //     the mirror entries and t.
+        double hn = 0.0;
+        if (hthr) {
+            const int a = tid;
+            if (a + 1 <= j + 1) {
+                const double up = (a + 1 < j + 1) ? mup : 1.0;
+                hn -= ((a == j) ? tau : tl[a]) * up;
+            }
+            if (a >= 1)
+                hn += ((a - 1 == j) ? tau : tl[a - 1]) * mdn;
+        }
+        ycol = ynext;
         if (multi && tid <= j + 1 && j + 1 < nb)
             hv[tid] = hn;
         if (tid == 0) {
@@ -801,7 +841,6 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
     ycol = __shfl(ycol, lane & ~(TPR - 1), 64);
     if (tid == 0) {
         pv.bc_fail = 0;
-        pv.hand_flag = 0u;
     }
     __syncthreads();
     const SlotIO sio(slots, base, local);

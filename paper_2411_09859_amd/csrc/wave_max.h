@@ -44,4 +44,23 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
     return ((unsigned long long)hi << 32) | lo;
 }
 
+// The same reduction on 32-bit keys: one DPP move and one max per stage.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned dpp_max_u32(unsigned x)
+{
+    const unsigned o = (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, ROWS, 0xf, false);
+    return (o > x) ? o : x;
+}
+
+__device__ __forceinline__ unsigned wave_max_u32(unsigned x)
+{
+    x = dpp_max_u32<0xb1, 0xf>(x);
+    x = dpp_max_u32<0x4e, 0xf>(x);
+    x = dpp_max_u32<0x141, 0xf>(x);
+    x = dpp_max_u32<0x140, 0xf>(x);
+    x = dpp_max_u32<0x142, 0xa>(x);
+    x = dpp_max_u32<0x143, 0xc>(x);
+    return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
+}
+
 }  // namespace skl
