@@ -345,23 +345,24 @@ __device__ __forceinline__ void find_pivot(PivotLds<NT / 64> &pl, const SlotIO &
 }
 
 
-// Lane I of each 16-lane row of the wave, in every lane of that row (one
-// 64-bit DPP move).
-template <int I>
-__device__ __forceinline__ double row_bcast(double h)
-{
-    // every lane's source lane exists (all lanes active), so no old value
-    return __longlong_as_double(
-        __builtin_amdgcn_mov_dpp(__double_as_longlong(h), 0x150 + I, 0xf, 0xf, false));
-}
-
 // acc[i & 3] += Lr[Q0 + i] * h[i] for the slots i < N of one 16-slot block,
-// h[i] being lane i of the row of hb.
+// h[i] being lane i of the row of hb: one FP64 FMA per slot with the row
+// broadcast as its DPP source operand (64-bit VALU operations accept DPP
+// with row_newbcast only).  The first of a block waits the two wait states a
+// DPP read needs after a VALU write of its source; volatile keeps that one
+// first.  Same product and rounding as fma(Lr, h, acc).
 template <int I, int N, int Q0, int LEN>
 __device__ __forceinline__ void bcast_fma(double (&acc)[4], const double (&Lr)[LEN], double hb)
 {
     if constexpr (I < N && Q0 + I < LEN) {
-        acc[I & 3] += Lr[Q0 + I] * row_bcast<I>(hb);
+        if constexpr (I == 0)
+            asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                         : "+v"(acc[I & 3])
+                         : "v"(hb), "v"(Lr[Q0 + I]), "i"(I));
+        else
+            asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                         : "+v"(acc[I & 3])
+                         : "v"(hb), "v"(Lr[Q0 + I]), "i"(I));
         bcast_fma<I + 1, N, Q0, LEN>(acc, Lr, hb);
     }
 }
