@@ -58,21 +58,26 @@ __device__ __forceinline__ bool beats(double av, int ai, double bv, int bi)
     return (aa > bb) | ((aa == bb) & (ai < bi));
 }
 
-// Wave-wide argmax in the pivot order; every lane receives the winner's
-// (v, idx, ph).  The bit pattern of |v| orders non-negative doubles, so the
-// largest is found on its high dword first (one 32-bit DPP max); the lanes
-// holding that high dword are found with a ballot, and only when several do
-// are their low dwords compared, and only on an exact tie the indices.
-// Lanes without a candidate hold v = 0, idx = INT_MAX.
+// Wave-wide argmax in the pivot order over the candidates in lanes
+// 0 .. CL-1 (CL = 16, 32 or 64; other lanes are ignored); every lane
+// receives the winner's (v, idx, ph).  The bit pattern of |v| orders
+// non-negative doubles, so the largest is found on its high dword first (one
+// 32-bit DPP max); the lanes holding that high dword are found with a
+// ballot, and only when several do are their low dwords compared, and only
+// on an exact tie the indices.  Lanes without a candidate hold v = 0,
+// idx = INT_MAX.
+template <int CL>
 __device__ __forceinline__ void wave_argmax(double &v, int &idx, int &ph)
 {
-    const unsigned long long key = (unsigned long long)__double_as_longlong(fabs(v));
+    const bool in = (CL == 64) || ((int)(threadIdx.x & 63) < CL);
+    const unsigned long long key =
+        in ? (unsigned long long)__double_as_longlong(fabs(v)) : 0ull;
     const unsigned khi = (unsigned)(key >> 32), klo = (unsigned)key;
-    const unsigned mh = wave_max_u32(khi);
-    bool top = (khi == mh);
+    const unsigned mh = lanes_max_u32<CL>(khi);
+    bool top = in && (khi == mh);
     unsigned long long m = __ballot(top);
     if (__popcll(m) != 1) {
-        const unsigned ml = wave_max_u32(top ? klo : 0u);
+        const unsigned ml = lanes_max_u32<CL>(top ? klo : 0u);
         top = top && (klo == ml);
         m = __ballot(top);
         if (__popcll(m) != 1) {
@@ -238,14 +243,15 @@ __device__ __forceinline__ void set_pivot(PivotLds<NW> &pl, double v, int idx, i
 // parity, and every group reduces them to the same pivot.  Ends with a
 // barrier after which pl.bc_* hold the pivot.  The caller's mirror stores
 // (this wave's) are complete before the slot is published.
-template <int NT>
+template <int NT, int CL>
 __device__ __forceinline__ void find_pivot(PivotLds<NT / 64> &pl, const SlotIO &sio, bool multi,
                                            int G, int w, int par, unsigned stamp, int r_cur, int n,
                                            int R, double cv, int ci, int cph)
 {
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    wave_argmax(cv, ci, cph);
+    static_assert(NW <= 16, "waves per group");
+    wave_argmax<CL>(cv, ci, cph);
     if (lane == 0) {
         pl.red_v[wave] = cv;
         pl.red_i[wave] = ci;
@@ -256,14 +262,23 @@ __device__ __forceinline__ void find_pivot(PivotLds<NT / 64> &pl, const SlotIO &
     if (multi)
         wait_vm();
     __syncthreads();
-    if (tid == 0) {
-        double bv;
-        int bi, bph;
-        reduce_waves<NW>(pl.red_v, pl.red_i, pl.red_ph, bv, bi, bph);
-        if (multi)
-            sio.publish(par * kSlotsPerParity + w, stamp, bv, bi, bph);
-        else
-            set_pivot<NW>(pl, bv, bi, bph, r_cur, n, G, R, sio.base);
+    // the group's candidate: wave 0 reduces the per-wave ones (lane q holds
+    // wave q's), then publishes it or, alone, takes it as the pivot
+    if (wave == 0) {
+        double bv = 0.0;
+        int bi = INT_MAX, bph = 0;
+        if (lane < NW) {
+            bv = pl.red_v[lane];
+            bi = pl.red_i[lane];
+            bph = pl.red_ph[lane];
+        }
+        wave_argmax<16>(bv, bi, bph);
+        if (lane == 0) {
+            if (multi)
+                sio.publish(par * kSlotsPerParity + w, stamp, bv, bi, bph);
+            else
+                set_pivot<NW>(pl, bv, bi, bph, r_cur, n, G, R, sio.base);
+        }
     }
 
     // several groups: poll all slots and reduce them identically in every
@@ -300,7 +315,7 @@ __device__ __forceinline__ void find_pivot(PivotLds<NT / 64> &pl, const SlotIO &
                 sio.fold(d0, gv, gi, gph);
             if (use1)
                 sio.fold(d1, gv, gi, gph);
-            wave_argmax(gv, gi, gph);
+            wave_argmax<64>(gv, gi, gph);
             if (lane == 0)
                 set_pivot<NW>(pl, gv, gi, gph, r_cur, n, G, R, sio.base);
         }
@@ -325,7 +340,7 @@ __device__ __forceinline__ void find_pivot(PivotLds<NT / 64> &pl, const SlotIO &
         }
         {
             if (wave * 64 < G)
-                wave_argmax(gv, gi, gph);
+                wave_argmax<64>(gv, gi, gph);
             __syncthreads(); // red_* of the group argmax were consumed by thread 0
             if (lane == 0) {
                 pl.red_v[wave] = gv;
@@ -539,7 +554,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(
                 ci = pos;
                 cph = phys;
             }
-            find_pivot<NT>(pv, sio, multi, G, w, par, stamp, r, n, R, cv, ci, cph);
+            find_pivot<NT, RL>(pv, sio, multi, G, w, par, stamp, r, n, R, cv, ci, cph);
         }
         const int p = pv.bc_p;
         const double tau = pv.bc_fail ? __longlong_as_double(0x7ff8000000000000ll) : pv.bc_tau;
@@ -872,7 +887,7 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
                 ci = pos;
                 cph = phys;
             }
-            find_pivot<NT>(pv, sio, multi, G, w, pr, stamp, r, n, R, cv, ci, cph);
+            find_pivot<NT, 64>(pv, sio, multi, G, w, pr, stamp, r, n, R, cv, ci, cph);
         }
         const int p = pv.bc_p;
         const double tau = pv.bc_fail ? qnan : pv.bc_tau;

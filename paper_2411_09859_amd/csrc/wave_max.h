@@ -52,13 +52,22 @@ __device__ __forceinline__ unsigned dpp_max_u32(unsigned x)
     return (o > x) ? o : x;
 }
 
-__device__ __forceinline__ unsigned wave_max_u32(unsigned x)
+// Largest value over lanes 0 .. CL-1 (CL = 16, 32 or 64), as a uniform
+// value: within 16-lane rows first, then rows 0-1 and the upper half as for
+// wave_max_u64.
+template <int CL>
+__device__ __forceinline__ unsigned lanes_max_u32(unsigned x)
 {
+    static_assert(CL == 16 || CL == 32 || CL == 64, "lane count");
     x = dpp_max_u32<0xb1, 0xf>(x);
     x = dpp_max_u32<0x4e, 0xf>(x);
     x = dpp_max_u32<0x141, 0xf>(x);
     x = dpp_max_u32<0x140, 0xf>(x);
+    if constexpr (CL == 16)
+        return (unsigned)__builtin_amdgcn_readlane((int)x, 0);
     x = dpp_max_u32<0x142, 0xa>(x);
+    if constexpr (CL == 32)
+        return (unsigned)__builtin_amdgcn_readlane((int)x, 31);
     x = dpp_max_u32<0x143, 0xc>(x);
     return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
 }
