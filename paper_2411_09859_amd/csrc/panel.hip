@@ -284,24 +284,27 @@ __device__ __forceinline__ void find_pivot(PivotLds<NT / 64> &pl, const SlotIO &
     // several groups: poll all slots and reduce them identically in every
     // group
     if (multi && G <= 128) {
-        // wave 0 alone: lane l polls slots l and l + 64 (both loads issued
-        // in every round; lanes past G read slot 0 and ignore it), then one
-        // wave argmax gives the pivot
+        // wave 0 alone: lane l polls slots l and l + 64 (a slot already
+        // seen complete is not read again; both reads of a round are in
+        // flight together), then one wave argmax gives the pivot
         if (wave == 0) {
             const int q0 = lane, q1 = lane + 64;
             const bool use0 = q0 < G, use1 = q1 < G;
             const int sb = par * kSlotsPerParity;
-            u32x4 d0, d1;
+            u32x4 d0 = {0u, 0u, 0u, 0u}, d1 = {0u, 0u, 0u, 0u};
+            bool ok0 = !use0, ok1 = !use1;
             long spins = 0;
             for (;;) {
                 // compiler-only fence: the slot loads are ordinary
                 // intrinsics and would otherwise be hoisted out of the spin
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                d0 = sio.load(sb + (use0 ? q0 : 0));
-                d1 = sio.load(sb + (use1 ? q1 : 0));
-                const bool ok = (!use0 || SlotIO::ready(d0, stamp)) &&
-                                (!use1 || SlotIO::ready(d1, stamp));
-                if (ok)
+                if (!ok0)
+                    d0 = sio.load(sb + q0);
+                if (!ok1)
+                    d1 = sio.load(sb + q1);
+                ok0 = ok0 || SlotIO::ready(d0, stamp);
+                ok1 = ok1 || SlotIO::ready(d1, stamp);
+                if (ok0 && ok1)
                     break;
                 if (pl.bc_fail || ++spins > kSpinLimit) {
                     pl.bc_fail = 1;
