@@ -179,14 +179,17 @@ int skltlt_pfaffian_partial(int n, const double *A, int lda, double *t,
 /* Largest order handled by skltlt_batched. */
 int skltlt_batched_max_n(void);
 
-/* Bytes of device workspace for skltlt_batched with `batch` matrices. */
+/* Bytes of device workspace for skltlt_batched with `batch` matrices: the
+ * work-queue counter and the processing order (4 bytes per matrix). */
 int skltlt_batched_workspace_size(int batch, size_t *bytes);
 
 /* Many independent small factorizations and Pfaffians in one persistent
  * kernel launch: each workgroup takes the next matrix from a queue and runs
  * the fused blocked algorithm of Sec. 3.6.3 on it with a small block size
  * (the two-step case b = 2 is Sec. 3.5.2), the panel's rows of L in the
- * workgroup's LDS and the trailing matrix in the caller's buffer.  No host
+ * workgroup's LDS and the trailing matrix in the caller's buffer.  The
+ * queue hands out the largest matrices first (a counting sort by n[i] on the
+ * device, in the same stream, ahead of the persistent launch).  No host
  * synchronization, no host staging: all descriptors are device arrays, so
  * the call can be captured in a hipGraph.
  *   batch        number of matrices (>= 0).

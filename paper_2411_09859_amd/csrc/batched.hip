@@ -436,6 +436,42 @@ __device__ void pfaffian_one(BatchShared &sh, int n, double *log_abs_pf, int *si
     }
 }
 
+// Processing order, largest matrices first (longest-processing-time-first
+// list scheduling: the persistent workgroups then finish within about one
+// small matrix of each other instead of one large one): a counting sort of
+// the batch indices by order n, descending, in one workgroup.  Orders outside
+// [0, kBT] (rejected later) go last.  Within one order the positions follow
+// the atomics' arrival; a matrix's arithmetic does not depend on it.
+constexpr int kOrdT = 1024;
+__global__ __launch_bounds__(kOrdT) void batch_order_kernel(int batch, const int *__restrict__ nv,
+                                                            int *__restrict__ order)
+{
+    constexpr int kKeys = kBT + 2; // key 0: invalid order, key n + 1: order n
+    __shared__ int cnt[kKeys];
+    const int tid = threadIdx.x;
+    for (int k = tid; k < kKeys; k += kOrdT)
+        cnt[k] = 0;
+    __syncthreads();
+    auto key_of = [&](int i) {
+        const int n = nv[i];
+        return (n >= 0 && n <= kBT) ? n + 1 : 0;
+    };
+    for (int i = tid; i < batch; i += kOrdT)
+        atomicAdd(&cnt[key_of(i)], 1);
+    __syncthreads();
+    if (tid == 0) { // first position of each key, largest key first
+        int run = 0;
+        for (int k = kKeys - 1; k >= 0; --k) {
+            const int c = cnt[k];
+            cnt[k] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < batch; i += kOrdT)
+        order[atomicAdd(&cnt[key_of(i)], 1)] = i;
+}
+
 __global__ __launch_bounds__(kBT) void batched_kernel(int batch, const int *__restrict__ nv,
                                                       double *const *__restrict__ Av,
                                                       const int *__restrict__ ldav,
@@ -444,14 +480,17 @@ __global__ __launch_bounds__(kBT) void batched_kernel(int batch, const int *__re
                                                       double *__restrict__ log_abs_pf,
                                                       int *__restrict__ sign,
                                                       int *__restrict__ info, int max_n,
-                                                      int block_size, int *__restrict__ queue)
+                                                      int block_size, int *__restrict__ queue,
+                                                      const int *__restrict__ order)
 {
     extern __shared__ double smem_b[];
     BatchShared &sh = *reinterpret_cast<BatchShared *>(smem_b);
     const int tid = threadIdx.x;
     for (;;) {
-        if (tid == 0)
-            sh.bc_idx = atomicAdd(queue, 1);
+        if (tid == 0) {
+            const int k = atomicAdd(queue, 1);
+            sh.bc_idx = (k < batch) ? order[k] : batch;
+        }
         __syncthreads();
         const int idx = sh.bc_idx;
         __syncthreads();
@@ -481,7 +520,7 @@ __global__ __launch_bounds__(kBT) void batched_kernel(int batch, const int *__re
 static hipError_t launch_batched(int batch, const int *n, double *const *A, const int *lda,
                                  double *const *t, int *const *ipiv, double *log_abs_pf,
                                  int *sign, int *info, int max_n, int block_size, int *queue,
-                                 hipStream_t s)
+                                 int *order, hipStream_t s)
 {
     static bool attr = false;
     if (!attr) {
@@ -494,6 +533,12 @@ static hipError_t launch_batched(int batch, const int *n, double *const *A, cons
     hipError_t e = launch_fill_zero(queue, 256, s);
     if (e != hipSuccess)
         return e;
+    {
+        void *oargs[] = {&batch, &n, &order};
+        e = hipLaunchKernel((const void *)batch_order_kernel, dim3(1), dim3(kOrdT), oargs, 0, s);
+        if (e != hipSuccess)
+            return e;
+    }
     int cus = device_cu_count();
     if (cus <= 0)
         cus = 256;
@@ -508,7 +553,7 @@ static hipError_t launch_batched(int batch, const int *n, double *const *A, cons
     if (grid < 1)
         return hipSuccess;
     void *args[] = {&batch, &n, &A, &lda, &t, &ipiv, &log_abs_pf, &sign, &info, &max_n,
-                    &block_size, &queue};
+                    &block_size, &queue, &order};
     return hipLaunchKernel((const void *)batched_kernel, dim3(grid), dim3(kBT), args,
                            sizeof(BatchShared), s);
 }
@@ -519,11 +564,18 @@ using namespace skl;
 
 extern "C" int skltlt_batched_max_n(void) { return kBT; }
 
+// the work-queue counter (256 bytes), then the processing order (one int per
+// matrix), rounded up to 256 bytes
+static size_t batched_work_bytes(int batch)
+{
+    return 256 + (((size_t)batch * sizeof(int) + 255) / 256) * 256;
+}
+
 extern "C" int skltlt_batched_workspace_size(int batch, size_t *bytes)
 {
     if (batch < 0 || !bytes)
         return SKLTLT_EINVAL;
-    *bytes = 256; // the work-queue counter
+    *bytes = batched_work_bytes(batch);
     return SKLTLT_OK;
 }
 
@@ -542,13 +594,13 @@ extern "C" int skltlt_batched(int batch, const int *n, double *const *A, const i
         return SKLTLT_EINVAL;
     if (batch == 0)
         return SKLTLT_OK;
-    if (!n || !A || !lda || !t || !ipiv || !work || work_bytes < 256 ||
+    if (!n || !A || !lda || !t || !ipiv || !work || work_bytes < batched_work_bytes(batch) ||
         ((uintptr_t)work % 4) != 0)
         return SKLTLT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const int ti = tm_begin(SKLTLT_K_BATCHED, s);
     const hipError_t e = launch_batched(batch, n, A, lda, t, ipiv, log_abs_pf, sign, info, max_n,
-                                        block_size, (int *)work, s);
+                                        block_size, (int *)work, (int *)((char *)work + 256), s);
     if (e != hipSuccess)
         return device_error(e, "batched launch");
     tm_end(ti, s, 0.0);
