@@ -182,14 +182,15 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
             // known with the pivot; every entry is read and written by one
             // thread only): issued here, their latency overlaps the rest of
             // the step up to the barrier
+            // (one load instruction for bv whichever side of p the row is
+            // on: loads in alternative branches into one register made the
+            // second wait for the first)
             const bool xrow = valid && i > r;
             double av = 0.0, bv = 0.0;
             if (xrow) {
                 av = A[(size_t)r * lda + i];
-                if (p != r && i > p)
-                    bv = A[(size_t)p * lda + i];
-                else if (p != r && i < p)
-                    bv = A[(size_t)i * lda + p];
+                if (p != r && i != p)
+                    bv = A[(i > p) ? (size_t)p * lda + i : (size_t)i * lda + p];
             }
             // row r hands its x to row p
             if (i == r)
