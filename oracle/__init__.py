@@ -36,6 +36,7 @@ MUTATIONS = {
     "wrong_l_column": 8,
     "partial_update_sign": 9,
     "partial_unscaled_l": 10,
+    "second_largest": 11,
 }
 
 

@@ -62,7 +62,8 @@ enum {
     MUT_LAST_INDEX_TIES = 7,  /* iamax keeps the last of equal magnitudes  */
     MUT_WRONG_L_COLUMN = 8,   /* l stored one column too far right         */
     MUT_PARTIAL_UPDATE_SIGN = 9, /* partial: X += c l^T - l c^T          */
-    MUT_PARTIAL_UNSCALED_L = 10  /* partial: l = x (not divided by tau)     */
+    MUT_PARTIAL_UNSCALED_L = 10, /* partial: l = x (not divided by tau)     */
+    MUT_SECOND_LARGEST = 11      /* iamax takes the second largest magnitude */
 };
 
 int oracle_ltlt(int n, const double *A, int lda, double *X, double *L,
@@ -129,6 +130,18 @@ int oracle_ltlt(int n, const double *A, int lda, double *X, double *L,
                 amax = a;
                 p = i;
             }
+        }
+        if (mutation == MUT_SECOND_LARGEST && r + 1 < n) {
+            int q = -1;
+            double bmax = -1.0;
+            for (int i = r; i < n; ++i) {
+                const double a = fabs(X_(i, k));
+                if (i != p && a > bmax) {
+                    bmax = a;
+                    q = i;
+                }
+            }
+            p = q;
         }
         /* Without pivoting (the unpivoted algorithms of Sec. 3.5 and 3.6,
          * for inputs known to need none) the pivot row is always r. */
