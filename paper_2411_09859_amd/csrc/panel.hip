@@ -754,6 +754,8 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
     constexpr int kNSR = ((kNS + kRing - 1) / kRing) * kRing;
     constexpr int NA = kNSR * TPR; // columns addressable through the ring
     static_assert(NA <= NT, "one thread per h entry");
+    static_assert(kNS % 16 == 0 && NA >= kNS * TPR, "h is read in blocks of 16 slots");
+    static_assert(TPR == 1 || TPR == 2 || TPR == 4, "a 16-lane row must hold one column class");
     extern __shared__ double stage[]; // R x 34, epilogue only
 
     __shared__ double hv[NA]; // h of the pair's first column
@@ -775,8 +777,11 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
         w >>= 3;
     }
     const int base = k0 + 1;
-    const int lr = tid / TPR;
-    const int sub = tid - lr * TPR;
+    // the TPR threads of a row are RL = 64 / TPR lanes apart, so each 16-lane
+    // row of a wave holds one column class and h is broadcast inside it
+    constexpr int RL = 64 / TPR;
+    const int lr = wave * RL + lane % RL;
+    const int sub = lane / RL;
     const int phys = w * R + lr;
     const int orow = base + phys;
     const bool multi = (G > 1);
@@ -815,35 +820,35 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
                 Lnew[i] = (i == slot) ? v : Lnew[i];
         }
     };
-    // x = y - sum_a M[row][a] h[a] over the filled columns
+    // x = y - sum_a M[row][a] h[a] over the filled columns: one LDS read of h
+    // per lane and block of 16 slots, each slot's value broadcast inside the
+    // 16-lane row as the FMA's DPP operand (slots of the unflushed group in
+    // Lreg are 0)
     auto gemv = [&](const double *h, double y) {
-        constexpr int kHB = 8; // (16 spills registers here)
+        const int hl = lane & 15;
+        double hb[kNS / 16];
+#pragma unroll
+        for (int k = 0; k < kNS / 16; ++k)
+            hb[k] = (16 * k < grc * kRing) ? h[sub + TPR * (16 * k + hl)] : 0.0; // uniform
+        const double hr = h[sub + TPR * (grc * kRing + (lane & (kRing - 1)))];
         double sacc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int qb = 0; qb < kNS; qb += kHB) {
-            if (qb < grc * kRing) {
-                double hh[kHB];
-#pragma unroll
-                for (int i = 0; i < kHB; ++i)
-                    hh[i] = (qb + i < kNS) ? h[sub + TPR * (qb + i)] : 0.0;
-#pragma unroll
-                for (int i = 0; i < kHB; ++i)
-                    if (qb + i < kNS)
-                        sacc[i & 3] += Lreg[qb + i] * hh[i];
-            }
-        }
-        {
-            double hh[kRing];
-#pragma unroll
-            for (int i = 0; i < kRing; ++i)
-                hh[i] = h[sub + TPR * (grc * kRing + i)];
-#pragma unroll
-            for (int i = 0; i < kRing; ++i)
-                sacc[i & 3] += Lnew[i] * hh[i];
-        }
+        if (0 < grc * kRing)
+            bcast_fma<0, 16, 0, kNS>(sacc, Lreg, hb[0]);
+        if constexpr (kNS > 16)
+            if (16 < grc * kRing)
+                bcast_fma<0, 16, 16, kNS>(sacc, Lreg, hb[1 % (kNS / 16)]);
+        if constexpr (kNS > 32)
+            if (32 < grc * kRing)
+                bcast_fma<0, 16, 32, kNS>(sacc, Lreg, hb[2 % (kNS / 16)]);
+        if constexpr (kNS > 48)
+            if (48 < grc * kRing)
+                bcast_fma<0, 16, 48, kNS>(sacc, Lreg, hb[3 % (kNS / 16)]);
+        static_assert(kNS <= 64, "h blocks");
+        bcast_fma<0, kRing, 0, kRing>(sacc, Lnew, hr);
         double sm = (sacc[0] + sacc[1]) + (sacc[2] + sacc[3]);
+        // the TPR partial sums of a row (lanes RL apart)
 #pragma unroll
-        for (int off = TPR >> 1; off >= 1; off >>= 1)
+        for (int off = 32; off >= RL; off >>= 1)
             sm += __shfl_xor(sm, off, 64);
         return y - sm;
     };
@@ -855,9 +860,8 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
     }
     for (int q = tid; q < nb; q += NT)
         wphys[q] = q;
-    if (exists && sub == 0)
+    if (exists) // every thread of the row (one address)
         ycol = W[(size_t)k0 * ldw + orow];
-    ycol = __shfl(ycol, lane & ~(TPR - 1), 64);
     if (tid == 0) {
         pv.bc_fail = 0;
     }
@@ -890,7 +894,7 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
                 ci = pos;
                 cph = phys;
             }
-            find_pivot<NT, 64>(pv, sio, multi, G, w, pr, stamp, r, n, R, cv, ci, cph);
+            find_pivot<NT, RL>(pv, sio, multi, G, w, pr, stamp, r, n, R, cv, ci, cph);
         }
         const int p = pv.bc_p;
         const double tau = pv.bc_fail ? qnan : pv.bc_tau;
@@ -905,10 +909,10 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
         }
         const bool nxt = (i + 1 < npair); // column c+2 belongs to this panel
         const int physE = (p == c + 2) ? physR0 : physE0; // row holding label c+2
-        double yo = 0.0, ye = 0.0;
-        if (exists && sub == 0 && pos > r)
+        double yo = 0.0, ye = 0.0; // every thread of a row loads (one address)
+        if (exists && pos > r)
             yo = W[(size_t)(base + physp) * ldw + orow];
-        if (nxt && exists && sub == 0 && pos > c + 2)
+        if (nxt && exists && pos > c + 2)
             ye = W[(size_t)(base + physE) * ldw + orow];
         const int a = tid;
         const bool ha = (a < 2 * i);
@@ -956,7 +960,7 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
         __syncthreads();
 
         // 3b. the pair's second column and c_i
-        ycol = __shfl(yo, lane & ~(TPR - 1), 64);
+        ycol = yo;
         const double xo = gemv(ho, ycol);
         insert(2 * i + 1, below ? xo : 0.0, below);
         if (below && sub == (2 * i + 1) % TPR)
@@ -982,7 +986,7 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
             }
             hv[a] = hn;
         }
-        ycol = __shfl(ye, lane & ~(TPR - 1), 64);
+        ycol = ye;
         if (tid == 0) {
             tl[i] = tau;
             pl[i] = p;
