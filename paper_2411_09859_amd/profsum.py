@@ -12,6 +12,12 @@ Subcommands:
       Writes the per-kernel table of a ``rocprofv3 --kernel-trace --stats -f
       csv`` run found under D (its ``*kernel_stats.csv``).
 
+  counters --dir D --kernel REGEX --counters C1,C2,... --source FILE[,FILE...]
+           --workload W --cmd "..." --out F [--cus N] [--algo-flops F]
+      Per-launch means of SQ/GRBM counters of one ``rocprofv3 --pmc`` run for
+      the kernels matching REGEX, the MFMA busy fraction and the F64 MFMA
+      operations as flops when those counters are present.
+
   traffic --fetch D1 --write D2 --calib-fetch D3 --calib-write D4 --mib M
           --kernel REGEX --source FILE[,FILE...] --algo-bytes B --cmd "..." --out F
       Per-launch HBM traffic of the kernels matching REGEX from two counter
@@ -153,6 +159,49 @@ def cmd_traffic(args):
     sys.stdout.write(txt)
 
 
+def cmd_counters(args):
+    """Per-launch means of SQ/GRBM counters for the kernels matching REGEX,
+    with the MFMA busy fraction and the F64 MFMA operations as flops (the
+    counter counts units of 512 flops) beside the algorithmic flops per
+    launch.  GRBM_GUI_ACTIVE of a dispatch is summed over the XCDs (each has
+    its own GRBM), so one XCD's active cycles are the value over the XCD
+    count, and the busy fraction is the MFMA busy cycles (summed over all
+    SIMDs) over those cycles times CUs times 4 SIMDs."""
+    names = [c.strip() for c in args.counters.split(",") if c.strip()]
+    per = {c: counter_per_dispatch(args.dir, c, args.kernel) for c in names}
+    nl = max((len(v) for v in per.values()), default=0)
+    if nl == 0:
+        raise SystemExit("kernel dispatches not found")
+    mean = {c: (sum(x for _, x in v.values()) / len(v) if v else float("nan"))
+            for c, v in per.items()}
+    lines = [f"# {args.title}", f"# command: {args.cmd}",
+             f"workload: {args.workload}", f"kernel_regex: {args.kernel}",
+             f"source: {args.source}", f"source_sha256: {sha256_of(args.source)}",
+             f"launches: {nl}"]
+    for c in names:
+        lines.append(f"{c}_per_launch: {mean[c]:.6e}")
+    if "SQ_VALU_MFMA_BUSY_CYCLES" in mean and "GRBM_GUI_ACTIVE" in mean:
+        act = mean["GRBM_GUI_ACTIVE"] / args.xcds
+        busy = mean["SQ_VALU_MFMA_BUSY_CYCLES"] / (act * args.cus * 4)
+        lines.append(f"active_cycles_per_launch_one_xcd: {act:.6e}")
+        lines.append(f"mfma_busy_fraction: {busy:.4f}")
+        if "SQ_BUSY_CU_CYCLES" in mean:
+            lines.append(f"cu_busy_fraction: {mean['SQ_BUSY_CU_CYCLES'] / (act * args.cus):.4f}")
+    if "SQ_INSTS_VALU_MFMA_MOPS_F64" in mean:
+        fl = mean["SQ_INSTS_VALU_MFMA_MOPS_F64"] * 512.0
+        lines.append(f"mfma_f64_flops_per_launch: {fl:.6e}")
+        if args.algo_flops:
+            lines.append(f"algorithmic_flops_per_launch: {args.algo_flops:.6e}")
+            lines.append(f"mfma_flops_over_algorithmic: {fl / args.algo_flops:.4f}")
+    if "SQ_LDS_BANK_CONFLICT" in mean and "SQ_INSTS_LDS" in mean and mean["SQ_INSTS_LDS"]:
+        lines.append(f"lds_bank_conflict_cycles_per_lds_instruction: "
+                     f"{mean['SQ_LDS_BANK_CONFLICT'] / mean['SQ_INSTS_LDS']:.4f}")
+    txt = "\n".join(lines) + "\n"
+    with open(args.out, "w") as f:
+        f.write(txt)
+    sys.stdout.write(txt)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="sub", required=True)
@@ -164,6 +213,18 @@ def main(argv=None):
     a.add_argument("--cmd", required=True)
     a.add_argument("--title", default="rocprofv3 kernel statistics")
     a.add_argument("--top", type=int, default=25)
+    a.add_argument("--out", required=True)
+    a = sub.add_parser("counters")
+    a.add_argument("--dir", required=True)
+    a.add_argument("--kernel", required=True)
+    a.add_argument("--counters", required=True)
+    a.add_argument("--cus", type=int, default=256)
+    a.add_argument("--xcds", type=int, default=8)
+    a.add_argument("--algo-flops", type=float, default=0.0)
+    a.add_argument("--source", required=True)
+    a.add_argument("--workload", required=True)
+    a.add_argument("--cmd", required=True)
+    a.add_argument("--title", default="rocprofv3 counters")
     a.add_argument("--out", required=True)
     a = sub.add_parser("traffic")
     for k in ("fetch", "write", "calib_fetch", "calib_write"):
@@ -180,7 +241,8 @@ def main(argv=None):
     a.add_argument("--workload", required=True, help='e.g. "n=16384 b=256"')
     a.add_argument("--out", required=True)
     args = ap.parse_args(argv)
-    {"copy": cmd_copy, "stats": cmd_stats, "traffic": cmd_traffic}[args.sub](args)
+    {"copy": cmd_copy, "stats": cmd_stats, "traffic": cmd_traffic,
+     "counters": cmd_counters}[args.sub](args)
 
 
 if __name__ == "__main__":
