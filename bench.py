@@ -82,22 +82,34 @@ def panel_flops(n, b):
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "skr2k_n16384_b256_traffic.txt")
+MFMA_SUMMARY = os.path.join(ROOT, "profiles", "skr2k_n16384_b256_mfma_counters.txt")
 
 
-def measured_traffic(n, b):
-    """Counter-measured HBM bytes per skr2k launch from the committed summary,
-    or None with the reason when it does not describe this kernel/workload."""
+def _committed_counters(path, n, b, key):
+    """A figure from a committed counter summary, or None with the reason
+    when the summary does not describe this kernel source and workload."""
     from paper_2411_09859_amd import profsum
-    if not os.path.exists(TRAFFIC_SUMMARY):
+    if not os.path.exists(path):
         return None, "no counter summary"
-    v = profsum.read_summary(TRAFFIC_SUMMARY)
+    v = profsum.read_summary(path)
     if v.get("workload") != f"n={n} b={b}":
         return None, "counters were taken at another workload"
     srcs = [os.path.join(ROOT, x.strip()) for x in v.get("source", "").split(",") if x.strip()]
     if not srcs or not all(os.path.exists(x) for x in srcs) or \
             profsum.sha256_of(",".join(srcs)) != v.get("source_sha256"):
         return None, "kernel source changed since the counters were taken"
-    return float(v["traffic_bytes_per_launch"]), os.path.relpath(TRAFFIC_SUMMARY, ROOT)
+    return float(v[key]), os.path.relpath(path, ROOT)
+
+
+def measured_traffic(n, b):
+    """Counter-measured HBM bytes per skr2k launch from the committed summary."""
+    return _committed_counters(TRAFFIC_SUMMARY, n, b, "traffic_bytes_per_launch")
+
+
+def measured_mfma_busy(n, b):
+    """Counter-measured MFMA busy fraction of the skr2k from the committed
+    summary."""
+    return _committed_counters(MFMA_SUMMARY, n, b, "mfma_busy_fraction")
 
 
 def resid_probe(torch, A0, Af, t, ipiv, nprobe=4, seed=0):
@@ -499,9 +511,11 @@ def main():
         achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
         bytes_per_launch = skr2k_bytes(n, b) * steps / sk["launches"]
         traffic, traffic_src = measured_traffic(n, b)
+        busy, busy_src = measured_mfma_busy(n, b)
         roof = {"kernel": "skr2k_kernel<double>", "bound": "mfma", "achieved": achieved,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                 "traffic": traffic, "traffic_source": traffic_src,
+                "mfma_busy": busy, "mfma_busy_source": busy_src,
                 "flops_per_launch": flops_per_launch,
                 "algorithmic_bytes_per_launch": bytes_per_launch,
                 "avg_launch_ms": per_launch_ms,
