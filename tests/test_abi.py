@@ -81,10 +81,21 @@ def test_factor_rejects_bad_arguments_without_device_work():
     assert L.skltlt_pfaffian(8, fake, 8, fake, fake, None, fake, 0, 0, fake, 1 << 20, None) == -1
 
 
-def test_batched_argument_checks():
+def test_batched_workspace_size():
+    """The queue counter (256 bytes) and the processing order (4 bytes per
+    matrix, rounded up to 256 bytes); a shorter workspace is refused before
+    anything is enqueued."""
     L = _lib_or_skip()
     sz = ctypes.c_size_t(0)
     assert L.skltlt_batched_workspace_size(-1, ctypes.byref(sz)) == -1
+    for batch, want in ((0, 256), (1, 512), (64, 512), (65, 768), (4096, 256 + 4 * 4096)):
+        assert L.skltlt_batched_workspace_size(batch, ctypes.byref(sz)) == 0
+        assert sz.value == want
+    fake = ctypes.c_void_p(0x1000)
+    for batch in (1, 4096):
+        L.skltlt_batched_workspace_size(batch, ctypes.byref(sz))
+        assert L.skltlt_batched(batch, fake, fake, fake, fake, fake, None, None, None, 16, 0, 0,
+                                fake, sz.value - 4, None) == binding.SKLTLT_EINVAL
 
 
 def test_batched_argument_checks():
