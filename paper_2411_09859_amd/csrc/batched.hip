@@ -107,27 +107,27 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
             const int r = c + 1;
             const bool last = (r == k0 + nb);
             // x = Y[., c] - L_p h, h = T_p L[c, panel]^T formed in the
-            // previous step (zero at j = 0)
+            // previous step (zero at j = 0).  Per block of 16 terms each lane
+            // reads one entry of h (lane m of a 16-lane row: term m) and the
+            // row's own 16 entries of L_p; every product is one FMA with the
+            // h entry broadcast inside the row as its DPP operand (one LDS
+            // read of h per 16 terms instead of one per term).  Every lane
+            // computes (the broadcast reads other lanes); rows that are not
+            // candidates discard the result.  Terms past column j are zero
+            // on both sides (LDS there may hold anything); four partial sums,
+            // term a into sum a % 4.
             const bool cand = valid && (i >= r);
-            double x = 0.0;
-            if (cand) {
-                // in blocks of 8 terms, all reads of a block issued before
-                // its products, four partial sums; entries past column j are
-                // masked (LDS there may hold anything)
-                double sp[4] = {0.0, 0.0, 0.0, 0.0};
-                for (int a0 = 0; a0 <= j; a0 += 8) {
-                    double lv[8], hh[8];
+            double sacc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int a0 = 0; a0 <= j; a0 += 16) { // uniform
+                const int am = a0 + (lane & 15);
+                const double hb = (am <= j) ? sh.hv[am] : 0.0;
+                double lv[16];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        lv[u] = (a0 + u <= j) ? sh.Lp[i][a0 + u] : 0.0;
-                        hh[u] = (a0 + u <= j) ? sh.hv[a0 + u] : 0.0;
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        sp[u & 3] += lv[u] * hh[u];
-                }
-                x = ycol - ((sp[0] + sp[1]) + (sp[2] + sp[3]));
+                for (int u = 0; u < 16; ++u)
+                    lv[u] = (a0 + u <= j) ? sh.Lp[i][a0 + u] : 0.0;
+                bcast_fma<0, 16, 0, 16>(sacc, lv, hb);
             }
+            double x = cand ? ycol - ((sacc[0] + sacc[1]) + (sacc[2] + sacc[3])) : 0.0;
             // argmax over the workgroup (first index on ties).  Per wave: the
             // largest |x| as its bit pattern (monotone for non-negative
             // doubles) by DPP moves, then the first candidate lane holding it

@@ -363,28 +363,6 @@ __device__ __forceinline__ void find_pivot(PivotLds<NT / 64> &pl, const SlotIO &
 }
 
 
-// acc[i & 3] += Lr[Q0 + i] * h[i] for the slots i < N of one 16-slot block,
-// h[i] being lane i of the row of hb: one FP64 FMA per slot with the row
-// broadcast as its DPP source operand (64-bit VALU operations accept DPP
-// with row_newbcast only).  The first of a block waits the two wait states a
-// DPP read needs after a VALU write of its source; volatile keeps that one
-// first.  Same product and rounding as fma(Lr, h, acc).
-template <int I, int N, int Q0, int LEN>
-__device__ __forceinline__ void bcast_fma(double (&acc)[4], const double (&Lr)[LEN], double hb)
-{
-    if constexpr (I < N && Q0 + I < LEN) {
-        if constexpr (I == 0)
-            asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-                         : "+v"(acc[I & 3])
-                         : "v"(hb), "v"(Lr[Q0 + I]), "i"(I));
-        else
-            asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-                         : "+v"(acc[I & 3])
-                         : "v"(hb), "v"(Lr[Q0 + I]), "i"(I));
-        bcast_fma<I + 1, N, Q0, LEN>(acc, Lr, hb);
-    }
-}
-
 template <int NT, int TPR, int kNS>
 __global__ __launch_bounds__(NT) void panel_kernel(
     double *__restrict__ A, int lda, const double *__restrict__ W, int ldw, int n, int k0,

@@ -1,6 +1,6 @@
 // Wave-level helpers shared by the panel and batched kernels: reading a
-// double from one lane, and the largest 64-bit key over a wave with DPP
-// moves (no LDS).
+// double from one lane, the largest key over a wave with DPP moves (no
+// LDS), and FP64 FMAs whose second factor is broadcast inside 16-lane rows.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -70,6 +70,29 @@ __device__ __forceinline__ unsigned lanes_max_u32(unsigned x)
         return (unsigned)__builtin_amdgcn_readlane((int)x, 31);
     x = dpp_max_u32<0x143, 0xc>(x);
     return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// acc[i & 3] += Lr[Q0 + i] * h[i] for the slots i < N of one 16-slot block,
+// h[i] being lane i of the row of hb: one FP64 FMA per slot with the row
+// broadcast as its DPP source operand (64-bit VALU operations accept DPP
+// with row_newbcast only).  The first of a block waits the two wait states a
+// DPP read needs after a VALU write of its source; volatile keeps that one
+// first.  Same product and rounding as fma(Lr, h, acc).  Every lane of the
+// wave must be active (each reads its row's source lane).
+template <int I, int N, int Q0, int LEN>
+__device__ __forceinline__ void bcast_fma(double (&acc)[4], const double (&Lr)[LEN], double hb)
+{
+    if constexpr (I < N && Q0 + I < LEN) {
+        if constexpr (I == 0)
+            asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                         : "+v"(acc[I & 3])
+                         : "v"(hb), "v"(Lr[Q0 + I]), "i"(I));
+        else
+            asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                         : "+v"(acc[I & 3])
+                         : "v"(hb), "v"(Lr[Q0 + I]), "i"(I));
+        bcast_fma<I + 1, N, Q0, LEN>(acc, Lr, hb);
+    }
 }
 
 }  // namespace skl
