@@ -134,10 +134,21 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
             // by a ballot (lanes are rows in order); then every thread
             // reduces the wave results in the same order (no serial step, no
             // extra barrier).
+            // (the largest high dword first, the low dwords compared only
+            // when several candidates share it)
             const unsigned long long key =
                 cand ? (unsigned long long)__double_as_longlong(fabs(x)) : 0ull;
-            const unsigned long long km = wave_max_u64(key);
-            const unsigned long long top = __ballot(cand && key == km);
+            // The DPP maxima run with every lane active (each reads other
+            // lanes), outside any condition.
+            const unsigned khi = (unsigned)(key >> 32);
+            const unsigned mh = lanes_max_u32<64>(khi);
+            const bool tophi = cand && (khi == mh);
+            unsigned long long top = __ballot(tophi);
+            if (__popcll(top) > 1) { // uniform
+                const unsigned klo = (unsigned)key;
+                const unsigned ml = lanes_max_u32<64>(tophi ? klo : 0u);
+                top = __ballot(tophi && klo == ml);
+            }
             double cv = 0.0;
             int ci = INT_MAX;
             if (top != 0) {

@@ -15,36 +15,8 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// One step of a 64-bit unsigned max over lanes with a DPP data movement
+// One step of a 32-bit unsigned max over lanes with a DPP data movement
 // (row_mask selects the rows that take the moved value; others keep theirs).
-template <int CTRL, int ROWS>
-__device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long x)
-{
-    const int lo = (int)(unsigned)x, hi = (int)(unsigned)(x >> 32);
-    const unsigned olo = (unsigned)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xf, false);
-    const unsigned ohi = (unsigned)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xf, false);
-    const unsigned long long o = ((unsigned long long)ohi << 32) | olo;
-    return (o > x) ? o : x;
-}
-
-// Largest value over the wave, in every lane: pairs and quads (quad_perm),
-// 8 and 16 lanes (row half mirror, row mirror), then lane 15 of each row into
-// the next and lane 31 into the upper half (row_bcast 15 / 31): lane 63 holds
-// the maximum, which is read back as a uniform value.  All VALU, no LDS.
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
-{
-    x = dpp_max_u64<0xb1, 0xf>(x);  // quad_perm [1,0,3,2]
-    x = dpp_max_u64<0x4e, 0xf>(x);  // quad_perm [2,3,0,1]
-    x = dpp_max_u64<0x141, 0xf>(x); // row_half_mirror
-    x = dpp_max_u64<0x140, 0xf>(x); // row_mirror
-    x = dpp_max_u64<0x142, 0xa>(x); // row_bcast:15 into rows 1 and 3
-    x = dpp_max_u64<0x143, 0xc>(x); // row_bcast:31 into rows 2 and 3
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, 63);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), 63);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
-// The same reduction on 32-bit keys: one DPP move and one max per stage.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ unsigned dpp_max_u32(unsigned x)
 {
@@ -53,8 +25,10 @@ __device__ __forceinline__ unsigned dpp_max_u32(unsigned x)
 }
 
 // Largest value over lanes 0 .. CL-1 (CL = 16, 32 or 64), as a uniform
-// value: within 16-lane rows first, then rows 0-1 and the upper half as for
-// wave_max_u64.
+// value: pairs and quads (quad_perm), 8 and 16 lanes (row half mirror, row
+// mirror), then lane 15 of each row into the next and lane 31 into the upper
+// half (row_bcast 15 / 31), the maximum ending in lane 0 (CL = 16), 31 or
+// 63.  All VALU, no LDS.
 template <int CL>
 __device__ __forceinline__ unsigned lanes_max_u32(unsigned x)
 {
