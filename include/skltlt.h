@@ -205,7 +205,7 @@ int skltlt_batched_workspace_size(int batch, size_t *bytes);
  *                rejected entry's buffers are not touched.
  *   max_n (host) upper bound of the n[i], at most skltlt_batched_max_n().
  *   block_size   0 = the autotuned choice for each n[i], else the panel
- *                width, at most 32 (SKLTLT_ENOTSUP above).
+ *                width, at most 16 (SKLTLT_ENOTSUP above).
  *   precision    SKLTLT_FP64 (SKLTLT_FP32_UPDATE returns SKLTLT_ENOTSUP).
  *   work (device), work_bytes: skltlt_batched_workspace_size bytes.
  * Each matrix's result depends only on that matrix and on (max_n,

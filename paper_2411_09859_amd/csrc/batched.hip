@@ -29,7 +29,14 @@
 namespace skl {
 
 constexpr int kBT = 256;     // threads per workgroup = largest order
-constexpr int kBMaxBs = 32;  // largest panel width (2 workgroups per CU)
+// largest panel width: the workgroup's LDS (the panel rows of L, 8 (kBMaxBs
+// + 1) bytes per row, 39 KB in all) then lets four workgroups share a CU
+// (with at most 128 VGPRs per thread: the launch bound below), which hides
+// more of each column step's latency than wider panels gain (measured on the
+// 4096-matrix batch: 3.12 ms at a largest width of 32 with two workgroups
+// per CU, 2.46 ms at 20 with three, 2.28 ms at 16 with four)
+constexpr int kBMaxBs = 16;
+constexpr int kBPerCu = 4;
 // LDS row of the panel's L: columns 0 .. kBMaxBs; the last slot also holds
 // the carried column between panels (moved to column 0 at the next panel's
 // start).  An odd number of doubles puts the rows read by one wave's lanes in
@@ -47,7 +54,7 @@ __device__ __host__ inline int batched_bs_for(int n)
 {
     for (const BatchedTune &e : kBatchedTune)
         if (n <= e.n_max)
-            return e.bs;
+            return e.bs < kBMaxBs ? e.bs : kBMaxBs;
     return kBMaxBs;
 }
 
@@ -484,7 +491,7 @@ __global__ __launch_bounds__(kOrdT) void batch_order_kernel(int batch, const int
         order[atomicAdd(&cnt[key_of(i)], 1)] = i;
 }
 
-__global__ __launch_bounds__(kBT) void batched_kernel(int batch, const int *__restrict__ nv,
+__global__ __launch_bounds__(kBT, kBPerCu) void batched_kernel(int batch, const int *__restrict__ nv,
                                                       double *const *__restrict__ Av,
                                                       const int *__restrict__ ldav,
                                                       double *const *__restrict__ tv,

@@ -4,13 +4,13 @@
 namespace skl {
 struct BatchedTune { int n_max; int bs; };
 constexpr BatchedTune kBatchedTune[] = {
-    {32, 32},
-    {64, 24},
-    {96, 20},
+    {32, 16},
+    {64, 16},
+    {96, 16},
     {128, 16},
-    {160, 24},
-    {192, 32},
-    {224, 32},
-    {256, 32},
+    {160, 16},
+    {192, 16},
+    {224, 16},
+    {256, 16},
 };
 }  // namespace skl

@@ -21,7 +21,7 @@ from .batch import Arena
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 CLASSES = [(16, 32), (34, 64), (66, 96), (98, 128), (130, 160), (162, 192), (194, 224), (226, 256)]
-CANDIDATES = [4, 8, 12, 16, 20, 24, 32]
+CANDIDATES = [4, 8, 12, 16]
 
 
 def time_arena(torch, arena, bs, reps=3):

@@ -101,9 +101,10 @@ def test_batched_workspace_size():
 def test_batched_argument_checks():
     """Argument checks of skltlt_batched run before anything is enqueued."""
     L = _lib_or_skip()
-    # panel width above the supported 32
-    assert L.skltlt_batched(1, None, None, None, None, None, None, None, None, 16, 33, 0, None, 0,
-                            None) == binding.SKLTLT_ENOTSUP
+    # panel width above the supported 16
+    for bs in (17, 33):
+        assert L.skltlt_batched(1, None, None, None, None, None, None, None, None, 16, bs, 0, None,
+                                0, None) == binding.SKLTLT_ENOTSUP
     # negative batch, orders above the kernel's 256
     assert L.skltlt_batched(-1, None, None, None, None, None, None, None, None, 16, 0, 0, None, 0,
                             None) == binding.SKLTLT_EINVAL

@@ -37,7 +37,7 @@ def test_batched_parity_mixed():
         check_against_oracle(M, r, check_pf=True)
 
 
-@pytest.mark.parametrize("bs", [1, 2, 3, 8, 16, 17, 24, 32])
+@pytest.mark.parametrize("bs", [1, 2, 3, 8, 12, 15, 16])
 def test_batched_block_sizes(bs):
     note(f"[batched] bs={bs}")
     mats = [inputs.skew_normal(n, 100 + n) for n in (5, 33, 100, 199, 256)]
