@@ -25,6 +25,7 @@
 // pivoted panel does; the trailing update is the same skr2k (identity
 // permutation).
 #include "common.h"
+#include "wave_max.h"
 
 namespace skl {
 
@@ -81,40 +82,57 @@ struct NpRow {
         }
     }
     // sum_a L[a] h[a] over this thread's filled columns (h in LDS, zero
-    // beyond the filled ones), summed over the row's TPR threads
+    // beyond the filled ones), summed over the row's TPR threads.  Per block
+    // of 16 slots each lane reads one entry of h (lane m of a 16-lane row:
+    // slot m of the block, for the row's column class) and every product is
+    // one FMA with that entry broadcast inside the row as its DPP operand;
+    // slots of the unflushed ring group in Lreg are 0.  Needs the lane
+    // layout of np_lane_row (a 16-lane row holds one column class) and every
+    // lane active.
     __device__ __forceinline__ double dot(const double *h, int sub) const
     {
-        constexpr int kHB = 8;
+        const int lane = threadIdx.x & 63;
+        const int hl = lane & 15;
+        constexpr int kNB = (kNpNS + 15) / 16;
+        static_assert(kNB <= 5, "h blocks");
+        double hb[kNB];
+#pragma unroll
+        for (int k = 0; k < kNB; ++k) // uniform conditions; in-range index
+            hb[k] = (16 * k < grc * kRing) ? h[min(sub + kNpTPR * (16 * k + hl), NA - 1)] : 0.0;
+        const double hr = h[sub + kNpTPR * (grc * kRing + (lane & (kRing - 1)))];
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int qb = 0; qb < kNpNS; qb += kHB) {
-            if (qb < grc * kRing) {
-                double hh[kHB];
-#pragma unroll
-                for (int i = 0; i < kHB; ++i)
-                    hh[i] = (qb + i < kNpNS) ? h[sub + kNpTPR * (qb + i)] : 0.0;
-#pragma unroll
-                for (int i = 0; i < kHB; ++i)
-                    if (qb + i < kNpNS)
-                        acc[i & 3] += Lreg[qb + i] * hh[i];
-            }
-        }
-        {
-            double hh[kRing];
-#pragma unroll
-            for (int i = 0; i < kRing; ++i)
-                hh[i] = h[sub + kNpTPR * (grc * kRing + i)];
-#pragma unroll
-            for (int i = 0; i < kRing; ++i)
-                acc[i & 3] += Lnew[i] * hh[i];
-        }
+        if (0 < grc * kRing)
+            bcast_fma<0, 16, 0, kNpNS>(acc, Lreg, hb[0]);
+        if constexpr (kNB > 1)
+            if (16 < grc * kRing)
+                bcast_fma<0, 16, 16, kNpNS>(acc, Lreg, hb[1 % kNB]);
+        if constexpr (kNB > 2)
+            if (32 < grc * kRing)
+                bcast_fma<0, 16, 32, kNpNS>(acc, Lreg, hb[2 % kNB]);
+        if constexpr (kNB > 3)
+            if (48 < grc * kRing)
+                bcast_fma<0, 16, 48, kNpNS>(acc, Lreg, hb[3 % kNB]);
+        if constexpr (kNB > 4)
+            if (64 < grc * kRing)
+                bcast_fma<0, 16, 64, kNpNS>(acc, Lreg, hb[4 % kNB]);
+        bcast_fma<0, kRing, 0, kRing>(acc, Lnew, hr);
         double s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 64 / kNpTPR, 64); // the row's other thread
         return s;
     }
     // after the last insert: every column in Lreg
     __device__ __forceinline__ void finish() { flush(grc); }
 };
+
+// Register row and column class of thread tid: the TPR threads of a row are
+// 64 / TPR lanes apart, so each 16-lane row of a wave holds one column class
+// (the broadcast of NpRow::dot).
+__device__ __forceinline__ void np_lane_row(int tid, int &lr, int &sub)
+{
+    constexpr int RL = 64 / kNpTPR;
+    lr = (tid >> 6) * RL + (tid & 63) % RL;
+    sub = (tid & 63) / RL;
+}
 
 // The row's outputs once its panel columns 0..nb are final: L columns into
 // A (column k0 + a is stored in A column k0 + a - 1, rows >= k0 + a + 1), the
@@ -180,8 +198,8 @@ __global__ __launch_bounds__(kNpNT) void nopiv_top_kernel(
     extern __shared__ double ltop[]; // nb x (nb + 2): the top rows' L, row-major
     const int ldt = nb + 2;
     const int tid = threadIdx.x;
-    const int lr = tid / kNpTPR;
-    const int sub = tid - lr * kNpTPR;
+    int lr, sub;
+    np_lane_row(tid, lr, sub);
     const int base = k0 + 1;
     const int i = base + lr; // this thread's row
     const bool mine = lr < nb;
@@ -275,8 +293,8 @@ __global__ __launch_bounds__(kNpNT) void nopiv_rows_kernel(
     __shared__ double tl[kNpMaxB];
     __shared__ double rtl[kNpMaxB]; // 1 / t (0 where t = 0)
     const int tid = threadIdx.x;
-    const int lr = tid / kNpTPR;
-    const int sub = tid - lr * kNpTPR;
+    int lr, sub;
+    np_lane_row(tid, lr, sub);
     const int cp = k0 + nb;
     const int i = cp + 1 + blockIdx.x * kNpR + lr;
     const bool mine = i < n;
