@@ -295,7 +295,7 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
         // every fourth block, kGrp at a time, their C loads issued before the
         // products.
         if (cp < n - 1) {
-            constexpr int kGrp = 4;
+            constexpr int kGrp = 2; // (4 spilled two VGPRs at four workgroups per CU)
             const int m = n - cp;
             const int nt = (m + 15) / 16;
             const int nblk = nt * (nt + 1) / 2;
