@@ -10,8 +10,9 @@ Reported value: GFLOP/s at the nominal n^3/3 flops of the paper (Sec. 3.6).
 Also reported: the same step with the FP32-MFMA update variant (backward error
 and Pfaffian difference stated), a per-kernel time breakdown measured with HIP
 events on the library's stream during the timed steps, the roofline of the
-dominant kernel, and the CPU oracle timed on a bounded sample (first column
-steps of the same matrix) on this host.
+dominant kernel (the panel, by time) and of the trailing update, the CPU
+oracle timed on the whole factorization of the same matrix on this host's
+cores, and the full-length comparison of both precisions with that oracle.
 """
 from __future__ import annotations
 
@@ -53,11 +54,12 @@ def kernel_times(lib):
     return out
 
 
-def skr2k_bytes(n, b):
-    """Algorithmic HBM bytes of all skr2k launches of one factorization: each
-    launch reads the strict lower triangle of the trailing block once (8 B
-    per element, at permuted positions), writes it and its negated mirror
-    (16 B per element) and reads the two m x K operand panels once."""
+def skr2k_bytes(n, b, per_elem=16.0):
+    """HBM bytes of all skr2k launches of one factorization: each launch reads
+    the strict lower triangle of the trailing block once and writes it
+    (per_elem = 16 B per element: the algorithmic minimum; 24 B with the
+    negated mirror store the full-storage design adds) and reads the two
+    m x K operand panels once."""
     tot = 0.0
     k0 = 0
     while k0 < n - 1:
@@ -66,9 +68,14 @@ def skr2k_bytes(n, b):
         m = n - cp
         if cp < n - 1 and m >= 2:
             K = 2 * ((nb + 1) // 2)
-            tot += 24.0 * m * (m - 1) / 2.0 + 16.0 * m * K
+            tot += per_elem * m * (m - 1) / 2.0 + 16.0 * m * K
         k0 = cp
     return tot
+
+
+def panel_tpr(b):
+    """Threads per register row of the panel kernel for panel width b."""
+    return 1 if b + 1 <= 65 else (2 if b + 1 <= 130 else 4)
 
 
 def panel_flops(n, b):
@@ -112,44 +119,112 @@ def measured_mfma_busy(n, b):
     return _committed_counters(MFMA_SUMMARY, n, b, "mfma_busy_fraction")
 
 
-def resid_probe(torch, A0, Af, t, ipiv, nprobe=4, seed=0):
-    """max over probes of ||(P A P^T - L T L^T) v|| / (||A||_F ||v||), O(n^2) each."""
+def unpack_L(torch, Af):
+    """Unit lower L from the packed layout (L[i][j+1] at (i, j), column 0 = e_0)."""
+    n = Af.shape[0]
+    L = torch.roll(torch.tril(Af, -2), shifts=1, dims=1)
+    L[:, 0] = 0
+    L += torch.eye(n, dtype=torch.float64, device=Af.device)
+    return L
+
+
+def permuted_full(torch, A0, ipiv_host):
+    """P A P^T of the full skew matrix whose strict lower triangle is A0's."""
     n = A0.shape[0]
+    qq = np.arange(n)
+    for r in range(n):
+        p = int(ipiv_host[r])
+        if p != r:
+            qq[r], qq[p] = qq[p], qq[r]
     low = torch.tril(A0, -1)
     Afull = low - low.T
     del low
-    q = torch.arange(n, device=A0.device)
-    piv = ipiv.to(torch.int64).cpu().numpy()
-    qq = np.arange(n)
-    for r in range(n):
-        p = int(piv[r])
-        if p != r:
-            qq[r], qq[p] = qq[p], qq[r]
     q = torch.from_numpy(qq).to(A0.device)
     PAP = Afull.index_select(0, q).index_select(1, q)
     del Afull
-    L = torch.tril(Af, -2)
-    L = torch.roll(L, shifts=1, dims=1)  # L[i][j+1] stored at (i, j)
-    L[:, 0] = 0
-    L = L + torch.eye(n, dtype=L.dtype, device=L.device)
-    normA = torch.linalg.norm(PAP).item()
-    g = torch.Generator(device=A0.device)
-    g.manual_seed(seed)
-    worst = 0.0
-    for _ in range(nprobe):
-        v = torch.randn(n, dtype=torch.float64, device=A0.device, generator=g)
-        w = L.T @ v
-        tw = torch.zeros_like(w)
-        tw[1:] += t * w[:-1]
-        tw[:-1] -= t * w[1:]
-        lhs = PAP @ v
-        rhs = L @ tw
-        worst = max(worst, (torch.linalg.norm(lhs - rhs) / (normA * torch.linalg.norm(v))).item())
-    del PAP, L
-    return worst
+    return PAP
 
 
-def bench_batched(torch, binding, inputs, count, seed=4, reps=3):
+def exact_residual(torch, A0, Af, t, ipiv_host):
+    """||P A P^T - L T L^T||_F / ||A||_F from one dense fp64 product."""
+    PAP = permuted_full(torch, A0, ipiv_host)
+    L = unpack_L(torch, Af)
+    LT = torch.zeros_like(L)  # (L T)[:, j] = t[j] L[:, j+1] - t[j-1] L[:, j-1]
+    LT[:, :-1] += L[:, 1:] * t[None, :]
+    LT[:, 1:] -= L[:, :-1] * t[None, :]
+    R = torch.matmul(LT, L.T.contiguous())
+    del LT, L
+    R -= PAP
+    out = (torch.linalg.norm(R) / torch.linalg.norm(PAP)).item()
+    del R, PAP
+    torch.cuda.empty_cache()
+    return out
+
+
+def compare_with_oracle(torch, Af, t, ipiv_host, ref):
+    """Pivots, t and L of a GPU factorization against the oracle's."""
+    L = unpack_L(torch, Af)
+    Lref = torch.from_numpy(np.asfortranarray(ref["L"])).to(Af.device)
+    l_rel = (torch.linalg.norm(L - Lref) / torch.linalg.norm(Lref)).item()
+    max_l = torch.max(torch.abs(L)).item()
+    del L, Lref
+    torch.cuda.empty_cache()
+    th = t.cpu().numpy()
+    eq = bool(np.array_equal(ipiv_host, ref["ipiv"]))
+    out = {"ipiv_equal_oracle_full": eq,
+           "t_rel_err": float(np.linalg.norm(th - ref["t"]) / np.linalg.norm(ref["t"])),
+           "L_rel_err": l_rel, "max_abs_L": max_l}
+    if not eq:
+        d = np.nonzero(ipiv_host != ref["ipiv"])[0]
+        out["pivot_steps_differing"] = int(d.size)
+        out["first_pivot_step_differing"] = int(d[0])
+    return out
+
+
+def host_info():
+    import platform
+    import subprocess
+    info = {"nproc": os.cpu_count(), "machine": platform.machine()}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            k = k.strip()
+            if k in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core"):
+                info[k] = v.strip()
+    except Exception as exc:  # lscpu missing: say so
+        info["lscpu"] = f"unavailable ({exc.__class__.__name__})"
+    return info
+
+
+def batched_vs_oracle(ar, sizes):
+    """Every member of a batch against the oracle: pivots, t, Pfaffian."""
+    import oracle
+    pp = ar.ipiv.cpu().numpy()
+    tt = ar.t.cpu().numpy()
+    las = ar.log_abs_pf.cpu().numpy()
+    sgs = ar.sign.cpu().numpy()
+    piv_ok = sign_ok = 0
+    worst_t = worst_pf = 0.0
+    for k in range(len(sizes)):
+        n = int(sizes[k])
+        M = ar.pristine[int(ar.offs[k]):int(ar.offs[k]) + n * n].cpu().numpy().reshape((n, n), order="F")
+        ref = oracle.ltlt(M, nthreads=1)
+        p = pp[int(ar.ioffs[k]):int(ar.ioffs[k]) + n]
+        piv_ok += int(np.array_equal(p, ref["ipiv"]))
+        if n > 1:
+            tk = tt[int(ar.toffs[k]):int(ar.toffs[k]) + n - 1]
+            nr = np.linalg.norm(ref["t"])
+            worst_t = max(worst_t, float(np.linalg.norm(tk - ref["t"]) / (nr if nr > 0 else 1.0)))
+        la, sg = oracle.pfaffian(n, ref["t"], ref["ipiv"])
+        sign_ok += int(sgs[k] == sg)
+        if sg != 0 and sgs[k] == sg:
+            worst_pf = max(worst_pf, abs(las[k] - la) / max(1.0, abs(la)))
+    return {"members": len(sizes), "ipiv_equal_oracle": piv_ok, "sign_equal_oracle": sign_ok,
+            "max_t_rel_err": worst_t, "max_rel_dlog_pf": worst_pf}
+
+
+def bench_batched(torch, binding, inputs, count, seed=4, reps=3, check=True):
     """4096 matrices, even n uniform over [16, 256], 5% singular: one batched
     launch vs a loop of per-matrix skltlt_pfaffian launches on one stream."""
     from paper_2411_09859_amd.batch import Arena
@@ -199,6 +274,11 @@ def bench_batched(torch, binding, inputs, count, seed=4, reps=3):
         graph_equal = graph_equal and np.array_equal(ar.sign.cpu().numpy(), signs) and \
             np.array_equal(ar.log_abs_pf.cpu().numpy(), logpf)
     ms = float(np.median(gts))
+    oracle_check = None
+    if check:
+        log(f"[bench] batched: every member against the oracle")
+        oracle_check = batched_vs_oracle(ar, sizes)
+        log(f"[bench] batched oracle check {oracle_check}")
     # baseline: per-matrix launches over a prefix of the same batch
     nbase = min(256, count)
     ar.restore()
@@ -222,6 +302,7 @@ def bench_batched(torch, binding, inputs, count, seed=4, reps=3):
            "graph_replays_equal_eager": bool(graph_equal), "pfaffians_per_s": count / (ms * 1e-3),
            "gflops_nominal": flops / (ms * 1e-3) / 1e9,
            "zero_pfaffians": int(np.sum(signs == 0)),
+           "oracle_check": oracle_check,
            "per_matrix_launch_baseline": {"matrices_timed": nbase, "ms_per_matrix": base_ms_per,
                                           "pfaffians_per_s": 1e3 / base_ms_per},
            "speedup_vs_per_matrix": (count / (ms * 1e-3)) / (1e3 / base_ms_per)}
@@ -229,33 +310,48 @@ def bench_batched(torch, binding, inputs, count, seed=4, reps=3):
     return out
 
 
-def bench_serving(torch, count, seed=5):
+def bench_serving(torch, count, short_count, seed=5, deadline=None):
     """Serving stream: n log-uniform over even values in [32, 2048], FP64 /
     FP32-update tags, 64 GB budget.  A closed-loop run (all requests at t=0)
-    measures capacity; Poisson runs at 50 %, 80 % and 95 % of it measure
-    latency under load."""
+    measures capacity; Poisson runs at 80 % (``count`` requests), 50 % and
+    95 % (``short_count``) of it measure latency under load.  A run that would
+    end after ``deadline`` (perf_counter seconds) is shortened, and the
+    request count actually run is stated."""
     from paper_2411_09859_amd.serving import GpuExecutor, Server, make_requests, summarize
+
+    def fit(want, rate):
+        if deadline is None:
+            return want
+        left = deadline - time.perf_counter()
+        return int(max(1000, min(want, 0.9 * left * rate)))
+
     reqs = make_requests(count, seed, rate_per_s=1.0)
     for r in reqs:
         r.arrival = 0.0
-    srv = Server(GpuExecutor(n_streams=4), budget_bytes=64 << 30)
+    srv = Server(GpuExecutor(n_streams=4), budget_bytes=64 << 30, keep_factors=False)
     t0 = time.perf_counter()
-    res = srv.run(reqs, time_limit_s=600)
+    res = srv.run(reqs, time_limit_s=900)
     wall = time.perf_counter() - t0
     closed = summarize(res, wall)
+    del res, srv
+    torch.cuda.empty_cache()
     cap = closed["solves_per_s"]
     log(f"[bench] serving closed loop {closed}")
-    out = {"workload": f"{count} requests (of the 100000-request stream), n log-uniform even in "
-                       f"[32,2048], FP64/FP32-update 50/50, Poisson arrivals, 64 GB budget",
+    out = {"workload": f"n log-uniform even in [32,2048], FP64/FP32-update 50/50, "
+                       f"factorization/Pfaffian 50/50, Poisson arrivals, 64 GB budget",
            "closed_loop": closed}
-    for pct, sd in ((80, seed + 1), (50, seed + 2), (95, seed + 3)):
+    for pct, sd, want in ((80, seed + 1, count), (50, seed + 2, short_count),
+                          (95, seed + 3, short_count)):
         rate = pct / 100.0 * cap
-        reqs = make_requests(count, sd, rate_per_s=rate)
-        srv = Server(GpuExecutor(n_streams=4), budget_bytes=64 << 30)
+        cnt = fit(want, rate)
+        reqs = make_requests(cnt, sd, rate_per_s=rate)
+        srv = Server(GpuExecutor(n_streams=4), budget_bytes=64 << 30, keep_factors=False)
         t0 = time.perf_counter()
-        res = srv.run(reqs, time_limit_s=600)
+        res = srv.run(reqs, time_limit_s=900)
         wall = time.perf_counter() - t0
         openl = summarize(res, wall)
+        del res, srv
+        torch.cuda.empty_cache()
         log(f"[bench] serving poisson at {pct}% {openl}")
         out[f"poisson_at_{pct}pct"] = dict(openl, rate_per_s=rate)
     return out
@@ -270,23 +366,32 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--fp32-steps", type=int, default=2)
-    ap.add_argument("--cpu-steps", type=int, default=160,
-                    help="oracle column steps in the CPU-baseline sample")
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="oracle column steps in the CPU baseline (0: the whole "
+                         "factorization, which also gives the full-length oracle checks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096)
-    ap.add_argument("--serving-count", type=int, default=2000,
-                    help="requests in the serving runs (the full stream has 100000)")
+    ap.add_argument("--serving-count", type=int, default=100000,
+                    help="requests in the closed-loop and 80 %% runs (the full stream)")
+    ap.add_argument("--serving-short", type=int, default=10000,
+                    help="requests in the 50 %% and 95 %% runs")
+    ap.add_argument("--time-budget", type=float, default=540.0,
+                    help="seconds the whole run may take; later serving runs shrink to fit")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--solve-steps", type=int, default=3,
                     help="timed solves with the factors (0: skip)")
     ap.add_argument("--partial-steps", type=int, default=2,
                     help="timed Pfaffian-only (partial) reductions (0: skip)")
+    ap.add_argument("--n8192-steps", type=int, default=3,
+                    help="timed factorizations of the n = 8192 N(0,1) matrix (0: skip)")
     ap.add_argument("--nopiv-steps", type=int, default=2,
                     help="timed unpivoted factorizations of a known-factor matrix (0: skip)")
     args = ap.parse_args()
 
+    t_start = time.perf_counter()
+    deadline = t_start + args.time_budget
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -350,11 +455,10 @@ def main():
 
     sign64 = int(sg.item())
     logpf64 = float(la.item())
-    ipiv64 = ipiv.clone()
+    ipiv64 = ipiv.cpu().numpy()
+    t64 = t.clone()
+    Af64 = Aw.clone()  # the FP64 factors, kept for the oracle comparison
     checks = {}
-    if not args.no_check:
-        checks["resid_probe_fp64"] = resid_probe(torch, A0, Aw, t, ipiv)
-        log(f"[bench] fp64 residual probe {checks['resid_probe_fp64']:.3e}")
 
     # solving A x = w with the factors just computed (one right-hand side)
     solve = None
@@ -494,72 +598,148 @@ def main():
                 "sign": int(sg.item()), "log_abs_pf": float(la.item()),
                 "sign_matches_fp64": int(sg.item()) == sign64,
                 "abs_dlog_pf_vs_fp64": abs(float(la.item()) - logpf64),
-                "pivots_equal_fp64": bool(torch.equal(ipiv, ipiv64))}
+                "pivots_equal_fp64": bool(np.array_equal(ipiv.cpu().numpy(), ipiv64))}
         if not args.no_check:
-            fp32["resid_probe"] = resid_probe(torch, A0, Aw, t, ipiv)
+            fp32["backward_error_exact"] = exact_residual(torch, A0, Aw, t, ipiv.cpu().numpy())
         log(f"[bench] FP32-update {fp32}")
 
-    # roofline of the throughput-bound kernel (the trailing update); the
-    # panel is latency-bound and reported by its per-step time
-    dom = max(("skr2k", "panel"), key=lambda k: kt.get(k, {}).get("total_ms", 0.0))
-    roof = None
+    fp32_ipiv = ipiv.cpu().numpy() if fp32 is not None else None
+
+    # the n = 8192 N(0,1) single-matrix workload at the block size the
+    # library's tuned table picks for that order
+    n8192 = None
+    if args.n8192_steps > 0:
+        n2 = 8192
+        b2 = binding.default_block_size(n2)
+        A2 = binding.to_device_colmajor(inputs.skew_normal(n2, 2, full=False))
+        A2w = torch.empty_like(A2)
+        t2 = torch.zeros(n2 - 1, dtype=torch.float64, device=dev)
+        ip2 = torch.zeros(n2, dtype=torch.int32, device=dev)
+        work2 = binding.alloc_workspace(binding.workspace_size(n2, b2, binding.FP64), dev)
+        ms2 = []
+        for s_ in range(args.n8192_steps + 1):
+            A2w.copy_(A2)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            binding.pfaffian(A2w, t2, ip2, la, sg, b2, binding.FP64, work2, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if s_ > 0:
+                ms2.append(e0.elapsed_time(e1))
+        m2 = float(np.median(ms2))
+        n8192 = {"workload": "n=8192 N(0,1) seed 2, FP64", "block_size": b2,
+                 "block_size_source": "tuned table (skltlt_default_block_size)",
+                 "ms": m2, "gflops_nominal": n2 ** 3 / 3.0 / (m2 * 1e-3) / 1e9,
+                 "frac_fp64_peak": n2 ** 3 / 3.0 / (m2 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+        del A2, A2w, work2
+        torch.cuda.empty_cache()
+        log(f"[bench] n=8192 {n8192}")
+
+    # roofline of each kernel class; the line's "roofline" is the dominant
+    # one by time, the other is reported beside it
+    steps = args.steps
+    roofs = {}
     if "skr2k" in kt:
         sk = kt["skr2k"]
-        steps = args.steps
         per_launch_ms = sk["total_ms"] / sk["launches"]
         flops_per_launch = sk["flops"] / sk["launches"]
         achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
-        bytes_per_launch = skr2k_bytes(n, b) * steps / sk["launches"]
+        alg = skr2k_bytes(n, b, 16.0) * steps / sk["launches"]
+        design = skr2k_bytes(n, b, 24.0) * steps / sk["launches"]
         traffic, traffic_src = measured_traffic(n, b)
         busy, busy_src = measured_mfma_busy(n, b)
-        roof = {"kernel": "skr2k_kernel<double>", "bound": "mfma", "achieved": achieved,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": traffic, "traffic_source": traffic_src,
-                "mfma_busy": busy, "mfma_busy_source": busy_src,
-                "flops_per_launch": flops_per_launch,
-                "algorithmic_bytes_per_launch": bytes_per_launch,
-                "avg_launch_ms": per_launch_ms,
-                "hbm_gbs_algorithmic": bytes_per_launch / (per_launch_ms * 1e-3) / 1e9,
-                "hbm_frac_algorithmic": bytes_per_launch / (per_launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                "dominant_class_by_time": dom}
+        roofs["skr2k"] = {
+            "kernel": "skr2k_kernel<double>", "bound": "mfma", "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": traffic, "traffic_source": traffic_src,
+            "traffic_over_algorithmic": (traffic / alg) if traffic else None,
+            "mfma_busy": busy, "mfma_busy_source": busy_src,
+            "flops_per_launch": flops_per_launch, "launches": sk["launches"] // steps,
+            "algorithmic_bytes_per_launch": alg,
+            "design_bytes_per_launch": design,
+            "avg_launch_ms": per_launch_ms,
+            "hbm_gbs_algorithmic": alg / (per_launch_ms * 1e-3) / 1e9,
+            "hbm_frac_algorithmic": alg / (per_launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
     panel = None
     if "panel" in kt:
         pk = kt["panel"]
-        pms = pk["total_ms"] / args.steps
+        pms = pk["total_ms"] / steps
+        launches = pk["launches"] // steps
         pf = panel_flops(n, b)
-        panel = {"bound": "latency", "ms_per_step": pms,
-                 "us_per_column_step": pms * 1e3 / (n - 1),
+        us_col = pms * 1e3 / (n - 1)
+        per_launch_ms = pk["total_ms"] / pk["launches"]
+        achieved = (pf / launches) / (per_launch_ms * 1e-3) / 1e12
+        panel = {"ms_per_step": pms, "us_per_column_step": us_col,
                  "alu_flops": pf, "alu_tflops": pf / (pms * 1e-3) / 1e12,
                  "alu_frac": pf / (pms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+        roofs["panel"] = {
+            "kernel": f"panel_kernel<512,{panel_tpr(b)},65>", "bound": "alu",
+            "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+            "flops_per_launch": pf / launches, "launches": launches,
+            "avg_launch_ms": per_launch_ms,
+            "latency": {"us_per_column_step": us_col, "budget_us_per_column_step": 2.0,
+                        "note": "bound by the latency of the per-column pivot exchange "
+                                "between workgroups, not by ALU or HBM"}}
+    dom = max(roofs, key=lambda k: kt[k]["total_ms"]) if roofs else None
+    roof = dict(roofs[dom], dominant_class_by_time=dom) if dom else None
+    roof_other = {k: v for k, v in roofs.items() if k != dom}
 
-    # CPU oracle on a bounded sample
+    # CPU oracle: the whole factorization of the same matrix on this host,
+    # which also gives the full-length checks of both precisions
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        nthr = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
-        s_steps = min(args.cpu_steps, n - 1)
-        log(f"[bench] oracle sample: first {s_steps} column steps, {nthr} threads")
-        tt = time.time()
-        oracle.ltlt(A_np, max_steps=0, nthreads=nthr)
-        t_setup = time.time() - tt
+        nthr = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        s_steps = n - 1 if args.cpu_steps <= 0 else min(args.cpu_steps, n - 1)
+        log(f"[bench] oracle: {s_steps} of {n - 1} column steps, {nthr} threads")
         tt = time.time()
         ref = oracle.ltlt(A_np, max_steps=s_steps, nthreads=nthr)
-        t_s = time.time() - tt - t_setup
+        t_s = time.time() - tt
+        del ref["X"]
         w_s = sum((n - k - 1) ** 2 for k in range(s_steps))
         w_all = sum((n - k - 1) ** 2 for k in range(n - 1))
-        t_full = t_s * w_all / w_s
-        cpu = {"value": nominal / t_full / 1e9, "unit": "GFLOP/s", "cores": nthr, "kind": "oracle",
-               "sample": (f"first {s_steps} of {n - 1} column steps of the same n={n} matrix "
-                          f"({t_s:.1f} s measured after {t_setup:.1f} s setup), extrapolated by the "
-                          f"per-step work (n-k-1)^2 to {t_full:.0f} s for the whole factorization")}
-        gp = ipiv64.cpu().numpy()
-        checks["oracle_prefix_steps"] = s_steps
-        checks["ipiv_prefix_equal_oracle"] = bool(np.array_equal(gp[: s_steps + 1],
-                                                                   ref["ipiv"][: s_steps + 1]))
+        host = host_info()
+        cpu = {"value": nominal * (w_s / w_all) / t_s / 1e9, "unit": "GFLOP/s", "cores": nthr,
+               "kind": "oracle", "seconds": t_s, "host": host}
+        if s_steps == n - 1:
+            cpu["sample"] = (f"the whole factorization of the same n={n} matrix (all {n - 1} "
+                             f"column steps), {t_s:.1f} s on {nthr} threads, GFLOP/s at the "
+                             f"nominal n^3/3")
+        else:
+            cpu["sample"] = (f"first {s_steps} of {n - 1} column steps of the same n={n} matrix "
+                             f"({t_s:.1f} s), scaled by their share (n-k-1)^2 of the work")
         log(f"[bench] oracle {cpu}")
+        if s_steps == n - 1 and not args.no_check:
+            la_o, sg_o = oracle.pfaffian(n, ref["t"], ref["ipiv"])
+            c64 = compare_with_oracle(torch, Af64, t64, ipiv64, ref)
+            c64["residual_exact"] = exact_residual(torch, A0, Af64, t64, ipiv64)
+            c64["sign_equal_oracle"] = sign64 == sg_o
+            c64["abs_dlog_pf_vs_oracle"] = abs(logpf64 - la_o)
+            checks["fp64_vs_oracle"] = c64
+            if fp32 is not None:
+                fp32["sign_matches_oracle"] = fp32["sign"] == sg_o
+                fp32["abs_dlog_pf_vs_oracle"] = abs(fp32["log_abs_pf"] - la_o)
+                fp32["rel_dlog_pf_vs_oracle"] = abs(fp32["log_abs_pf"] - la_o) / max(1.0, abs(la_o))
+                fp32["pivots_equal_oracle"] = bool(np.array_equal(fp32_ipiv, ref["ipiv"]))
+                fp32["pivot_steps_equal_oracle"] = int(np.sum(fp32_ipiv == ref["ipiv"]))
+            checks["oracle_pfaffian"] = {"sign": sg_o, "log_abs_pf": la_o}
+            log(f"[bench] checks {checks}")
+        elif s_steps < n - 1:
+            checks["oracle_prefix_steps"] = s_steps
+            checks["ipiv_prefix_equal_oracle"] = bool(np.array_equal(ipiv64[: s_steps + 1],
+                                                                       ref["ipiv"][: s_steps + 1]))
+        del ref
+    elif not args.no_check:
+        checks["residual_exact_fp64"] = exact_residual(torch, A0, Af64, t64, ipiv64)
+    del Af64
 
-    batched = None if args.no_batched else bench_batched(torch, binding, inputs, args.batch_count)
-    serving = None if args.no_serving else bench_serving(torch, args.serving_count)
+    batched = None if args.no_batched else bench_batched(torch, binding, inputs, args.batch_count,
+                                                         check=not args.no_check)
+    serving = None if args.no_serving else bench_serving(
+        torch, args.serving_count, args.serving_short, deadline=deadline)
 
     out = {
         "metric": "FP64 skew-LTLt GFLOP/s (n^3/3) at n=16384; batched Pfaffians/s + p99 latency",
@@ -578,12 +758,14 @@ def main():
                                f"N(0,1)*10^U(-6,6), seed {args.seed}, FP64",
                    "n": n, "block_size": b},
         "roofline": roof,
+        "roofline_other": roof_other,
         "step_ms": {"mean": ms, "median": float(np.median(step_ms)), "min": float(np.min(step_ms)),
                     "max": float(np.max(step_ms))},
         "panel": panel,
         "solve": solve,
         "pfaffian_partial": partial,
         "nopiv": nopiv,
+        "n8192": n8192,
         "cpu_baseline": cpu,
         "kernels": kt,
         "fp32_update": fp32,
@@ -591,8 +773,13 @@ def main():
         "batched": batched,
         "serving": serving,
         "checks": checks,
+        "elapsed_s": time.perf_counter() - t_start,
     }
     print(json.dumps(out), flush=True)
+    # release the timing events and finish all device work before the
+    # runtime's teardown at exit
+    torch.cuda.synchronize()
+    lib.skltlt_timing_release()
 
 
 if __name__ == "__main__":

@@ -202,7 +202,8 @@ int skltlt_batched_workspace_size(int batch, size_t *bytes);
  *                the Pfaffians.
  *   info (device) batch ints or NULL: 0 = done, -1 = entry rejected
  *                (n[i] < 0, n[i] > max_n or lda[i] < max(1, n[i])); a
- *                rejected entry's buffers are not touched.
+ *                rejected entry's matrix, t and ipiv are not touched, and
+ *                its log_abs_pf / sign (when given) are set to NaN / 0.
  *   max_n (host) upper bound of the n[i], at most skltlt_batched_max_n().
  *   block_size   0 = the autotuned choice for each n[i], else the panel
  *                width, at most 16 (SKLTLT_ENOTSUP above).
@@ -269,6 +270,11 @@ int skltlt_timing_enable(int max_launches);
 
 /* Stop recording (events are kept until the next enable). */
 int skltlt_timing_disable(void);
+
+/* Destroys the events skltlt_timing_enable created (recording stops), so
+ * that a measurement tool can release them before the HIP runtime is torn
+ * down at process exit. */
+int skltlt_timing_release(void);
 
 /* Synchronizes the recorded events and returns, for one kernel class, the
  * summed duration in milliseconds and the number of timed launches (host

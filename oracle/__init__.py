@@ -87,7 +87,8 @@ def ltlt(A: np.ndarray, max_steps: int = -1, nthreads: int = 0, mutation: int | 
     Returns a dict with ``X`` (state after the steps; T when complete), ``L``
     (unit lower, first column e_0), ``t`` (n-1 subdiagonal entries of T) and
     ``ipiv`` (absolute, 0-based, ipiv[0] = 0).  The relation P A P^T = L T L^T
-    holds with P built from ``ipiv`` by :func:`perm_from_ipiv`.  With
+    holds with P the product of the transpositions (r, ipiv[r]) applied in
+    order r = 1, 2, ... (P(pi) of Sec. 3.7.1 with absolute pivots).  With
     ``pivot=False`` every step pivots on its own subdiagonal entry (P = I),
     the unpivoted algorithm for inputs known to need no pivoting.
     """
@@ -158,21 +159,6 @@ def pack(L: np.ndarray, t: np.ndarray, A: np.ndarray) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle_pack failed")
     return out
-
-
-def perm_from_ipiv(ipiv: np.ndarray) -> np.ndarray:
-    """Index vector q with (P A P^T)[i, j] = A[q[i], q[j]].
-
-    P = P(pi_{n-1}) ... P(pi_0) (Sec. 3.7.1) with absolute pivots: the
-    transpositions (r, ipiv[r]) are applied in order r = 0, 1, ... to the rows.
-    """
-    n = len(ipiv)
-    q = np.arange(n)
-    for r in range(n):
-        p = int(ipiv[r])
-        if p != r:
-            q[r], q[p] = q[p], q[r]
-    return q
 
 
 def solve(A: np.ndarray, B: np.ndarray) -> np.ndarray:

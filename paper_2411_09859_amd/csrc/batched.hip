@@ -520,8 +520,15 @@ __global__ __launch_bounds__(kBT, kBPerCu) void batched_kernel(int batch, const 
         const bool ok = (n >= 0) && (n <= max_n) && (n <= kBT) && (lda >= (n > 1 ? n : 1));
         if (info && tid == 0)
             info[idx] = ok ? 0 : -1;
-        if (!ok)
+        if (!ok) {
+            // a rejected member's matrix, t and ipiv are not touched; its
+            // Pfaffian outputs say that there is no result
+            if (log_abs_pf && sign && tid == 0) {
+                log_abs_pf[idx] = __longlong_as_double(0x7ff8000000000000ll);
+                sign[idx] = 0;
+            }
             continue;
+        }
         const int bs = block_size > 0 ? block_size : batched_bs_for(n);
         for (int q = tid; q < kBT; q += kBT) {
             sh.tl[q] = 0.0;
@@ -598,10 +605,10 @@ extern "C" int skltlt_batched_workspace_size(int batch, size_t *bytes)
     return SKLTLT_OK;
 }
 
-extern "C" int skltlt_batched(int batch, const int *n, double *const *A, const int *lda,
-                              double *const *t, int *const *ipiv, double *log_abs_pf, int *sign,
-                              int *info, int max_n, int block_size, int precision, void *work,
-                              size_t work_bytes, void *stream)
+// Argument checks of the batched call (before any device work).
+static int batched_check(int batch, const int *n, double *const *A, const int *lda,
+                         double *const *t, int *const *ipiv, const double *log_abs_pf,
+                         const int *sign, int max_n, int block_size, int precision)
 {
     if (batch < 0 || max_n < 0 || max_n > kBT || block_size < 0 || block_size > kBMaxBs)
         return block_size > kBMaxBs || max_n > kBT ? SKLTLT_ENOTSUP : SKLTLT_EINVAL;
@@ -611,10 +618,21 @@ extern "C" int skltlt_batched(int batch, const int *n, double *const *A, const i
         return SKLTLT_EINVAL;
     if ((log_abs_pf == nullptr) != (sign == nullptr))
         return SKLTLT_EINVAL;
-    if (batch == 0)
-        return SKLTLT_OK;
-    if (!n || !A || !lda || !t || !ipiv || !work || work_bytes < batched_work_bytes(batch) ||
-        ((uintptr_t)work % 4) != 0)
+    if (batch > 0 && (!n || !A || !lda || !t || !ipiv))
+        return SKLTLT_EINVAL;
+    return SKLTLT_OK;
+}
+
+extern "C" int skltlt_batched(int batch, const int *n, double *const *A, const int *lda,
+                              double *const *t, int *const *ipiv, double *log_abs_pf, int *sign,
+                              int *info, int max_n, int block_size, int precision, void *work,
+                              size_t work_bytes, void *stream)
+{
+    int st = batched_check(batch, n, A, lda, t, ipiv, log_abs_pf, sign, max_n, block_size,
+                           precision);
+    if (st != SKLTLT_OK || batch == 0)
+        return st;
+    if (!work || work_bytes < batched_work_bytes(batch) || ((uintptr_t)work % 4) != 0)
         return SKLTLT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const int ti = tm_begin(SKLTLT_K_BATCHED, s);

@@ -5,7 +5,7 @@
 // applies the panel's pivots to the rows of all earlier columns of L
 // (pivot_rows in the code of Fig. "C++ implementation", Sec. 4.2); the paper
 // measures this as its largest pivoted overhead because rows are exchanged in
-// column-major storage (Sec. 5.2).  The right-looking update never reads those
+// column-major storage (Sec. 5.3).  The right-looking update never reads those
 // columns again, so here every column of L receives all of its later
 // exchanges at once at the end: column j gets the composition of the
 // transpositions of all steps after the panel that last wrote it, applied as

@@ -72,6 +72,21 @@ extern "C" int skltlt_timing_disable(void)
     return SKLTLT_OK;
 }
 
+extern "C" int skltlt_timing_release(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_on = false;
+    g_used = 0;
+    int st = SKLTLT_OK;
+    for (Rec &r : g_pool) {
+        if (hipEventDestroy(r.a) != hipSuccess || hipEventDestroy(r.b) != hipSuccess)
+            st = SKLTLT_EDEVICE;
+    }
+    g_pool.clear();
+    g_pool.shrink_to_fit();
+    return st;
+}
+
 extern "C" int skltlt_timing_read(int kernel_class, double *total_ms, int *launches,
                                   double *flops)
 {

@@ -5,13 +5,20 @@ arrival order while the device-memory budget allows (back-pressure when it is
 full), keeps every admitted request's matrix and factors on the device, and
 overlaps their work on the GPU:
 
-* small FP64 requests (n <= ``small_n``) are collected and factored together
-  by one ``skltlt_batched`` launch; requests admitted while a batch runs join
-  the next batch, which starts as soon as the batch stream is free;
-* the others run alone, spread over a pool of streams: a factorization
-  request by ``skltlt_pfaffian`` (its factors are handed back on the
-  device), a Pfaffian request by ``skltlt_pfaffian_partial`` (half the pivot
-  steps, nothing but the Pfaffian).
+* small requests (n <= ``small_n``) are collected and factored together by
+  one ``skltlt_batched`` launch, in FP64 whatever their tag (the batched
+  kernel runs FP64 only; FP64 is at least as accurate as the FP32-update
+  variant asked for, and at these orders the update is a small share of the
+  work); requests admitted while a batch runs join the next batch, which
+  starts as soon as the batch stream is free;
+* the others run alone, spread over a pool of streams, in the precision
+  their tag asks for: a factorization request by ``skltlt_pfaffian`` (its
+  factors are handed back on the device), a Pfaffian request by
+  ``skltlt_pfaffian_partial`` (half the pivot steps, nothing but the
+  Pfaffian).
+
+Each result records the precision it was computed in (``precision_used``).
+A batched member the library rejects (``info != 0``) comes back as an error.
 
 Completion is detected by polling HIP events, never by blocking the device.
 Latency is measured from a request's arrival to the host observing its
@@ -58,6 +65,8 @@ class Result:
     path: str
     error: Optional[str] = None
     factors: object = None
+    precision: int = 0          # the request's tag
+    precision_used: int = 0     # the precision it was computed in
 
     @property
     def latency(self):
@@ -110,11 +119,12 @@ class FakeExecutor:
         out = []
         for _, reqs, path in done:
             for r in reqs:
+                used = 0 if path == "batched" else r.precision
                 if self.fail and self.fail(r):
-                    out.append((r, float("nan"), 0, path, "device error", None))
+                    out.append((r, float("nan"), 0, path, "device error", None, used))
                     continue
                 la, sg = self.pf(r) if self.pf else (0.0, 1)
-                out.append((r, la, sg, path, None, None))
+                out.append((r, la, sg, path, None, None, used))
         return out
 
     def idle(self):
@@ -179,13 +189,15 @@ class GpuExecutor:
                             binding.FP64, work, s)
             la_h = torch.empty(len(reqs), dtype=torch.float64, pin_memory=True)
             sg_h = torch.empty(len(reqs), dtype=torch.int32, pin_memory=True)
+            in_h = torch.empty(len(reqs), dtype=torch.int32, pin_memory=True)
             la_h.copy_(la, non_blocking=True)
             sg_h.copy_(sg, non_blocking=True)
+            in_h.copy_(info, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
         keep = (mats, ts, ps, n_dev, lda, A_ptr, t_ptr, p_ptr, la, sg, info, work)
         facs = [(mats[k], ts[k], ps[k]) if r.factor else None for k, r in enumerate(reqs)]
-        self.inflight.append((ev, ("batched", reqs, la_h, sg_h, keep, facs)))
+        self.inflight.append((ev, ("batched", reqs, la_h, sg_h, keep, facs, in_h)))
 
     def launch_single(self, req):
         torch, binding = self.torch, self.binding
@@ -212,7 +224,8 @@ class GpuExecutor:
             ev.record(s)
         path = "single" if req.factor else "partial"
         facs = [(A, t, ip)] if req.factor else [None]
-        self.inflight.append((ev, (path, [req], la_h, sg_h, (A, t, ip, la, sg, work), facs)))
+        self.inflight.append((ev, (path, [req], la_h, sg_h, (A, t, ip, la, sg, work), facs,
+                                   None)))
 
     def batch_busy(self):
         return any(p[0] == "batched" for _, p in self.inflight)
@@ -221,9 +234,13 @@ class GpuExecutor:
         out, keep = [], []
         for ev, payload in self.inflight:
             if ev.query():
-                path, reqs, la_h, sg_h, bufs, facs = payload
+                path, reqs, la_h, sg_h, bufs, facs, in_h = payload
                 for k, r in enumerate(reqs):
-                    out.append((r, float(la_h[k]), int(sg_h[k]), path, None, facs[k]))
+                    err = None
+                    if in_h is not None and int(in_h[k]) != 0:
+                        err = f"rejected by the batched kernel (info {int(in_h[k])})"
+                    used = 0 if path == "batched" else r.precision
+                    out.append((r, float(la_h[k]), int(sg_h[k]), path, err, facs[k], used))
             else:
                 keep.append((ev, payload))
         self.inflight = keep
@@ -238,8 +255,13 @@ class Server:
 
     def __init__(self, executor, budget_bytes: int = 64 << 30, small_n: int = 256,
                  max_batch: int = 4096, max_inflight_single: int = 64,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, keep_factors: bool = True):
         self.ex = executor
+        # keep_factors=False: a factorization request's device factors are
+        # released when it completes (a client that reads only the Pfaffian;
+        # otherwise every completed request would keep its matrix on the
+        # device for as long as its result is held)
+        self.keep_factors = keep_factors
         self.budget = budget_bytes
         self.small_n = small_n
         self.max_batch = max_batch
@@ -296,12 +318,14 @@ class Server:
 
     def _collect(self):
         now = self.clock()
-        for r, la, sg, path, err, facs in self.ex.poll():
+        for r, la, sg, path, err, facs, used in self.ex.poll():
             self.used -= self.held.pop(r.rid)
             if path != "batched":
                 self.inflight_single -= 1
             self.results.append(Result(r.rid, r.n, la, sg, r.arrival,
-                                       self.admit_time.pop(r.rid), now, path, err, facs))
+                                       self.admit_time.pop(r.rid), now, path, err,
+                                       facs if self.keep_factors else None,
+                                       r.precision, used))
 
     def tick(self):
         self._collect()
@@ -348,6 +372,12 @@ def summarize(results, wall_s: float):
         "mean_ms": float(lat.mean() * 1e3),
         "batched_fraction": float(np.mean([r.path == "batched" for r in ok])) if ok else 0.0,
         "partial_fraction": float(np.mean([r.path == "partial" for r in ok])) if ok else 0.0,
+        "by_tag": {tag: {"requests": sum(r.precision == p for r in results),
+                         "computed_fp64": sum(r.precision == p and r.precision_used == 0
+                                              for r in ok),
+                         "computed_fp32_update": sum(r.precision == p and r.precision_used == 1
+                                                     for r in ok)}
+                   for tag, p in (("fp64", 0), ("fp32_update", 1))},
     }
 
 

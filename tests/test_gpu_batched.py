@@ -79,6 +79,9 @@ def test_batched_rejects_invalid_members():
     res = db.results()
     assert res[0]["info"] == 0 and res[1]["info"] == -1 and res[2]["info"] == -1
     assert np.array_equal(res[1]["A"], big)
+    for r in res[1:]:  # no result: NaN log|Pf| and sign 0, t and ipiv untouched
+        assert np.isnan(r["log_abs_pf"]) and r["sign"] == 0
+        assert np.all(r["t"] == -5.0) and np.all(r["ipiv"] == -1)
     check_against_oracle(good, res[0], check_pf=True)
 
 

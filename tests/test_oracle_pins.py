@@ -471,3 +471,20 @@ def test_oracle_solve_reads_strict_lower_only():
     assert np.array_equal(oracle.solve(A, B), oracle.solve(junk, B))
     low = np.tril(A, -1)
     assert np.linalg.norm((low - low.T) @ oracle.solve(A, B) - B) < 1e-10
+
+
+def test_perm_index_is_the_product_of_transpositions():
+    """The index vector the checks use for P A P^T equals the explicit
+    product P = P_{n-1} ... P_1 of the exchange matrices P(pi) of Sec. 3.7.1
+    (absolute pivots: P_r exchanges rows r and ipiv[r])."""
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 5, 9, 16):
+        ipiv = np.array([0] + [int(rng.integers(r, n)) for r in range(1, n)], dtype=np.int32)
+        P = np.eye(n)
+        for r in range(1, n):
+            Pr = np.eye(n)
+            Pr[[r, ipiv[r]]] = Pr[[ipiv[r], r]]
+            P = Pr @ P
+        A = rng.standard_normal((n, n))
+        q = ck.perm_index(ipiv)
+        assert np.array_equal(P @ A @ P.T, A[np.ix_(q, q)])
