@@ -217,6 +217,29 @@ int skltlt_batched(int batch, const int *n, double *const *A, const int *lda,
                    int precision, void *work, size_t work_bytes,
                    void *stream);
 
+/* ---- Allocation-free batched call ---------------------------------------
+ * For callers that cannot allocate device memory or pass a workspace: code
+ * under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  skltlt_batched with the same arguments minus work/work_bytes:
+ * the queue counter and processing order live in a static device array of
+ * 256 + 4 * skltlt_batched_noalloc_max_batch() bytes (1 MiB + 256 B), one per
+ * device, which the process holds until it ends; its device address is
+ * looked up once per device on the first call made with that device
+ * current.  The call allocates nothing and clears what must start at zero
+ * with a kernel (no memset), so it can be captured in a hipGraph.
+ * Every call on a device shares that device's array: two calls that overlap
+ * in time on one device (different streams or threads, not ordered by the
+ * caller) race on it and may both produce wrong results.  Calls on one
+ * stream, or ordered by events, are safe.
+ * Returns SKLTLT_ENOTSUP for batch > skltlt_batched_noalloc_max_batch();
+ * other arguments, results and errors as for skltlt_batched. */
+int skltlt_batched_noalloc_max_batch(void);
+int skltlt_batched_noalloc(int batch, const int *n, double *const *A,
+                           const int *lda, double *const *t,
+                           int *const *ipiv, double *log_abs_pf, int *sign,
+                           int *info, int max_n, int block_size,
+                           int precision, void *stream);
+
 /* Text of the HIP error behind the most recent SKLTLT_EDEVICE returned in
  * the calling thread ("" if none).  Static storage, never NULL. */
 const char *skltlt_last_device_error(void);

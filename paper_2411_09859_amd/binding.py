@@ -76,6 +76,10 @@ def lib():
         L.skltlt_batched_workspace_size.restype = i
         L.skltlt_batched.argtypes = [i, vp, vp, vp, vp, vp, vp, vp, vp, i, i, i, vp, sz, vp]
         L.skltlt_batched.restype = i
+        L.skltlt_batched_noalloc_max_batch.argtypes = []
+        L.skltlt_batched_noalloc_max_batch.restype = i
+        L.skltlt_batched_noalloc.argtypes = [i, vp, vp, vp, vp, vp, vp, vp, vp, i, i, i, vp]
+        L.skltlt_batched_noalloc.restype = i
         L.skltlt_solve_workspace_size.argtypes = [i, i, ctypes.POINTER(sz)]
         L.skltlt_solve_workspace_size.restype = i
         L.skltlt_solve.argtypes = [i, i, vp, i, vp, vp, vp, i, vp, sz, vp]
@@ -267,6 +271,24 @@ def batched(n_dev, A_ptrs, lda_dev, t_ptrs, ipiv_ptrs, log_abs_pf, sign, info, m
                               work.numel(), _stream(stream))
     if st != SKLTLT_OK:
         raise SkltltError(st, "skltlt_batched")
+    return st
+
+
+def batched_noalloc_max_batch() -> int:
+    return lib().skltlt_batched_noalloc_max_batch()
+
+
+def batched_noalloc(n_dev, A_ptrs, lda_dev, t_ptrs, ipiv_ptrs, log_abs_pf, sign, info,
+                    max_n: int, block_size: int = 0, precision: int = FP64, stream=None):
+    """skltlt_batched_noalloc: as batched() with no workspace (the library's
+    per-device static scratch array)."""
+    batch = n_dev.numel()
+    st = lib().skltlt_batched_noalloc(batch, _ptr(n_dev), _ptr(A_ptrs), _ptr(lda_dev),
+                                      _ptr(t_ptrs), _ptr(ipiv_ptrs), _ptr(log_abs_pf),
+                                      _ptr(sign), _ptr(info), int(max_n), int(block_size),
+                                      int(precision), _stream(stream))
+    if st != SKLTLT_OK:
+        raise SkltltError(st, "skltlt_batched_noalloc")
     return st
 
 

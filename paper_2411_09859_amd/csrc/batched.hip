@@ -25,6 +25,7 @@
 
 #include <climits>
 #include <cmath>
+#include <mutex>
 
 namespace skl {
 
@@ -605,7 +606,7 @@ extern "C" int skltlt_batched_workspace_size(int batch, size_t *bytes)
     return SKLTLT_OK;
 }
 
-// Argument checks of the batched call (before any device work).
+// Argument checks shared by both batched entry points.
 static int batched_check(int batch, const int *n, double *const *A, const int *lda,
                          double *const *t, int *const *ipiv, const double *log_abs_pf,
                          const int *sign, int max_n, int block_size, int precision)
@@ -638,6 +639,72 @@ extern "C" int skltlt_batched(int batch, const int *n, double *const *A, const i
     const int ti = tm_begin(SKLTLT_K_BATCHED, s);
     const hipError_t e = launch_batched(batch, n, A, lda, t, ipiv, log_abs_pf, sign, info, max_n,
                                         block_size, (int *)work, (int *)((char *)work + 256), s);
+    if (e != hipSuccess)
+        return device_error(e, "batched launch");
+    tm_end(ti, s, 0.0);
+    return SKLTLT_OK;
+}
+
+// ---- allocation-free variant ------------------------------------------------
+// The queue counter and the processing order live in a file-scope device
+// array instead of a caller's workspace: one copy per device, held by the
+// process until it ends.  In host code `scratch` only names the symbol; its
+// device address is looked up once per device with hipGetSymbolAddress and
+// that address is what the kernels receive.
+constexpr int kNoAllocMaxBatch = 1 << 18;
+constexpr size_t kNoAllocScratchBytes = 256 + (size_t)kNoAllocMaxBatch * sizeof(int);
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static void *g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of this device's copy of `scratch` (looked up on the first
+// call made with that device current).
+static int scratch_of_current_device(char **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return device_error(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return SKLTLT_ENOTSUP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return device_error(e, "hipGetSymbolAddress(scratch)");
+        if (!p || ((uintptr_t)p % 256) != 0)
+            return device_error(hipErrorInvalidSymbol, "scratch address");
+        g_scratch_dev[dev] = p;
+    }
+    *out = (char *)g_scratch_dev[dev];
+    return SKLTLT_OK;
+}
+
+extern "C" int skltlt_batched_noalloc_max_batch(void) { return kNoAllocMaxBatch; }
+
+extern "C" int skltlt_batched_noalloc(int batch, const int *n, double *const *A, const int *lda,
+                                      double *const *t, int *const *ipiv, double *log_abs_pf,
+                                      int *sign, int *info, int max_n, int block_size,
+                                      int precision, void *stream)
+{
+    int st = batched_check(batch, n, A, lda, t, ipiv, log_abs_pf, sign, max_n, block_size,
+                           precision);
+    if (st != SKLTLT_OK || batch == 0)
+        return st;
+    if (batch > kNoAllocMaxBatch)
+        return SKLTLT_ENOTSUP;
+    char *sp = nullptr;
+    if ((st = scratch_of_current_device(&sp)) != SKLTLT_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int ti = tm_begin(SKLTLT_K_BATCHED, s);
+    // the queue counter (first 256 bytes) is cleared by a kernel in
+    // launch_batched; the order array is rewritten entirely by every call
+    const hipError_t e = launch_batched(batch, n, A, lda, t, ipiv, log_abs_pf, sign, info, max_n,
+                                        block_size, (int *)sp, (int *)(sp + 256), s);
     if (e != hipSuccess)
         return device_error(e, "batched launch");
     tm_end(ti, s, 0.0);

@@ -110,3 +110,20 @@ def test_batched_argument_checks():
                             None) == binding.SKLTLT_EINVAL
     assert L.skltlt_batched(1, None, None, None, None, None, None, None, None, 257, 0, 0, None, 0,
                             None) == binding.SKLTLT_ENOTSUP
+
+
+def test_noalloc_batched_limits():
+    """The allocation-free batched call states its limit and refuses larger
+    batches (and bad arguments) before touching the device."""
+    L = _lib_or_skip()
+    mx = L.skltlt_batched_noalloc_max_batch()
+    assert mx == 1 << 18
+    fake = 256  # never dereferenced: the call returns before any device work
+    assert L.skltlt_batched_noalloc(mx + 1, fake, fake, fake, fake, fake, None, None, None,
+                                    16, 0, 0, None) == binding.SKLTLT_ENOTSUP
+    assert L.skltlt_batched_noalloc(-1, fake, fake, fake, fake, fake, None, None, None,
+                                    16, 0, 0, None) == binding.SKLTLT_EINVAL
+    assert L.skltlt_batched_noalloc(4, fake, fake, fake, fake, fake, None, None, None,
+                                    16, 0, 1, None) == binding.SKLTLT_ENOTSUP
+    assert L.skltlt_batched_noalloc(0, None, None, None, None, None, None, None, None,
+                                    16, 0, 0, None) == binding.SKLTLT_OK
