@@ -16,8 +16,10 @@ constexpr int kSlotsPerParity = kMaxPanelGroups;
 constexpr size_t kAlign = 256;
 
 // Pivot exchange slots: one 16-byte record per panel workgroup and step
-// parity (layout in the panel kernel), one L2 line apart.
+// parity (layout in the panel kernel), one L2 line apart, then one 4-byte
+// record per workgroup for the launch's XCD check.
 constexpr int kSlotBytes = 128;
+constexpr size_t kSlotArrayBytes = (size_t)kSlotBytes * 3 * kSlotsPerParity;
 struct Slot {
     unsigned int w[4];
 };
@@ -32,7 +34,7 @@ struct FactorWs {
     double *lcar;      // carried L column (n doubles)
     double *uv;        // skr2k operands, column-major n x (4*nq): [U | V | -V | U]
     float *uv32;       // same in fp32
-    Slot *slots;       // 2 * kMaxPanelGroups
+    Slot *slots;       // kSlotArrayBytes: 2 parities x kMaxPanelGroups, XCD check
     int *gmap;         // nblocks x n suffix gather maps
     int *blk_k0;       // nblocks + 1 block starts (device copy not needed: args)
     size_t bytes;

@@ -104,8 +104,9 @@ __device__ __forceinline__ void st_dev(double *p, double v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Stores read only by groups on the same XCD: a plain store is acknowledged
-// by the shared L2, and device-scope loads on that XCD observe it.
+// A store read by other groups: plain when every working group shares this
+// XCD (checked at the launch's start; the shared L2 makes it visible to their
+// device-scope reads), device scope otherwise.
 __device__ __forceinline__ void st_xcd(double *p, double v, bool local)
 {
     if (local)
@@ -130,7 +131,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 struct SlotIO {
     __amdgpu_buffer_rsrc_t srs;
     int base;   // the panel's first trailing row
-    bool local; // every group on one XCD
+    bool local; // every working group on this XCD (checked at the launch's start)
 
     __device__ __forceinline__ SlotIO(Slot *slots, int base_, bool local_)
         : srs(__builtin_amdgcn_make_buffer_rsrc((void *)slots, (short)0,
@@ -363,6 +364,80 @@ __device__ __forceinline__ void find_pivot(PivotLds<NT / 64> &pl, const SlotIO &
 }
 
 
+__device__ __forceinline__ double dbl_of(unsigned lo, unsigned hi)
+{
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// One step of an xor butterfly over the lanes OFF = 32 or 16 apart: every
+// lane gets s + s(lane ^ OFF), with the gfx950 lane-swap instructions (VALU,
+// no LDS).  Swapping a register with itself leaves, in the two outputs, the
+// lane's own half and the partner half, so their sum is the butterfly step
+// (the same sum as s + shfl_xor(s, OFF): addition commutes).
+template <int OFF>
+__device__ __forceinline__ double xor_add(double s)
+{
+    static_assert(OFF == 32 || OFF == 16, "swap distance");
+    const unsigned long long b = (unsigned long long)__double_as_longlong(s);
+    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+    if constexpr (OFF == 32) {
+        const auto l2 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h2 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        return dbl_of(l2[0], h2[0]) + dbl_of(l2[1], h2[1]);
+    } else {
+        const auto l2 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h2 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        return dbl_of(l2[0], h2[0]) + dbl_of(l2[1], h2[1]);
+    }
+}
+
+// Whether every working group of this launch runs on one XCD: each group
+// publishes its XCC_ID (hardware register) tagged with the panel's first
+// column and reads all the others' (device scope).  Every group reaches the
+// same answer from the same records.  The exchange then uses plain stores,
+// which the XCD's shared L2 makes visible to the device-scope reads of its
+// other groups; otherwise every cross-group store is device scope.  A failed
+// wait answers "no" and poisons the panel.
+__device__ __forceinline__ bool groups_share_xcd(Slot *slots, int G, int w, int k0, int &fail)
+{
+    __shared__ int same;
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)((char *)slots + (size_t)2 * kSlotsPerParity * kSlotBytes), (short)0,
+            (int)(kSlotBytes * kSlotsPerParity), 0x00020000);
+        unsigned xcc;
+        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
+        const unsigned tag = ((unsigned)(k0 + 1) & 0x0fffffffu) << 4;
+        if (tid == 0)
+            __builtin_amdgcn_raw_buffer_store_b32(tag | (xcc & 0xfu), rs, w * kSlotBytes, 0, 16);
+        bool ok = true, lfail = false;
+        for (int q = tid; q < G; q += 64) {
+            unsigned v = 0;
+            long spins = 0;
+            for (;;) {
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                v = __builtin_amdgcn_raw_buffer_load_b32(rs, q * kSlotBytes, 0, 16);
+                if ((v & ~0xfu) == tag)
+                    break;
+                if (++spins > kSpinLimit) {
+                    lfail = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            ok = ok && !lfail && ((v & 0xfu) == (xcc & 0xfu));
+        }
+        const bool all = __ballot(!ok) == 0;
+        if (__ballot(lfail) != 0 && tid == 0)
+            fail = 1;
+        if (tid == 0)
+            same = all ? 1 : 0;
+    }
+    __syncthreads();
+    return same != 0;
+}
+
 template <int NT, int TPR, int kNS>
 __global__ __launch_bounds__(NT) void panel_kernel(
     double *__restrict__ A, int lda, const double *__restrict__ W, int ldw, int n, int k0,
@@ -397,9 +472,9 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     const int lane = tid & 63;
     // With one_xcd the grid holds 8 workgroups per panel group and only those
     // with an id divisible by 8 work: workgroup ids are dealt round-robin to
-    // the 8 XCDs, so all working groups share one XCD, which shortens the
-    // device-scope round trips of the exchange (correctness does not depend
-    // on the placement, every cross-group access is device-scope).
+    // the 8 XCDs, so the working groups normally share one XCD; the kernel
+    // checks that (XCC_ID) before it lets the exchange use plain stores, so
+    // correctness does not depend on the placement, only the speed does.
     int w = blockIdx.x;
     if (one_xcd) {
         if (w & 7)
@@ -415,7 +490,6 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     const int phys = w * R + lr;    // its row in the mirror (fixed)
     const int orow = base + phys;   // its row of the panel-start matrix (fixed)
     const bool multi = (G > 1);
-    const bool local = (one_xcd != 0);
 
     // The matrix row a register row represents.  Exchanging rows r and p
     // relabels the two register rows instead of moving their data: the one
@@ -449,19 +523,27 @@ __global__ __launch_bounds__(NT) void panel_kernel(
         hv[a] = 0.0;
     for (int a = tid; a < NA; a += NT)
         hrow[a] = 0.0;
-    if (exists && sub == 0) {
-        const double l0 = (k0 == 0) ? 0.0 : lcar[pos];
-        Lnew[0] = l0;
-        if (multi)
-            st_xcd(&mirror[(size_t)phys * ldm], l0, local);
-    }
+    if (exists && sub == 0)
+        Lnew[0] = (k0 == 0) ? 0.0 : lcar[pos];
     if (exists) // every thread of the row (one address)
         ycol = W[(size_t)k0 * ldw + orow];
     if (tid == 0) {
         pv.bc_fail = 0;
     }
     __syncthreads();
+    // with one_xcd, whether the working groups did land on one XCD (then the
+    // exchange uses plain stores)
+    bool local = false;
+    if (one_xcd) {
+        int fl = 0;
+        local = groups_share_xcd(slots, G, w, k0, fl);
+        if (fl && tid == 0)
+            pv.bc_fail = 1;
+    }
     const SlotIO sio(slots, base, local);
+    // the carried column's mirror entry
+    if (multi && exists && sub == 0)
+        st_xcd(&mirror[(size_t)phys * ldm], Lnew[0], local);
 
     for (int j = 0; j < nb; ++j) {
         const int c = k0 + j;
@@ -520,9 +602,10 @@ __global__ __launch_bounds__(NT) void panel_kernel(
         bcast_fma<0, kRing, 0, kRing>(sacc, Lnew, hr);
         double s = (sacc[0] + sacc[1]) + (sacc[2] + sacc[3]);
         // the TPR partial sums of a row (lanes RL apart)
-#pragma unroll
-        for (int off = 32; off >= RL; off >>= 1)
-            s += __shfl_xor(s, off, 64);
+        if constexpr (RL <= 32)
+            s = xor_add<32>(s);
+        if constexpr (RL <= 16)
+            s = xor_add<16>(s);
         const double xv = ycol - s;
 
         // 3-4. group argmax, then (several groups) the exchange of the
@@ -763,7 +846,6 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
     const int phys = w * R + lr;
     const int orow = base + phys;
     const bool multi = (G > 1);
-    const bool local = (one_xcd != 0);
     int pos = orow;
     const bool exists = (orow < n);
 
@@ -825,9 +907,10 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
         bcast_fma<0, kRing, 0, kRing>(sacc, Lnew, hr);
         double sm = (sacc[0] + sacc[1]) + (sacc[2] + sacc[3]);
         // the TPR partial sums of a row (lanes RL apart)
-#pragma unroll
-        for (int off = 32; off >= RL; off >>= 1)
-            sm += __shfl_xor(sm, off, 64);
+        if constexpr (RL <= 32)
+            sm = xor_add<32>(sm);
+        if constexpr (RL <= 16)
+            sm = xor_add<16>(sm);
         return y - sm;
     };
 
@@ -844,6 +927,15 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
         pv.bc_fail = 0;
     }
     __syncthreads();
+    // with one_xcd, whether the working groups did land on one XCD (then the
+    // exchange uses plain stores)
+    bool local = false;
+    if (one_xcd) {
+        int fl = 0;
+        local = groups_share_xcd(slots, G, w, k0, fl);
+        if (fl && tid == 0)
+            pv.bc_fail = 1;
+    }
     const SlotIO sio(slots, base, local);
     const double qnan = __longlong_as_double(0x7ff8000000000000ll);
 

@@ -67,7 +67,7 @@ size_t factor_ws_layout(int n, int b, FactorWs *ws, char *base)
     w.lcar = (double *)take(sizeof(double) * nn);
     w.uv = (double *)take(sizeof(double) * nn * (size_t)(4 * nq));
     w.uv32 = (float *)take(sizeof(float) * nn * (size_t)(4 * nq));
-    w.slots = (Slot *)take((size_t)kSlotBytes * 2 * kSlotsPerParity);
+    w.slots = (Slot *)take(kSlotArrayBytes);
     w.gmap = (int *)take(sizeof(int) * nn * (size_t)nblk);
     w.blk_k0 = nullptr;
     w.bytes = off;
@@ -186,7 +186,7 @@ static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int bloc
             return device_error(e, "set ipiv");
         if (!pivot && (e = launch_iota(ws.perm, n, s)) != hipSuccess)
             return device_error(e, "identity permutation");
-        if (n > 1 && (e = launch_fill_zero(ws.slots, (size_t)kSlotBytes * 2 * kSlotsPerParity, s)) !=
+        if (n > 1 && (e = launch_fill_zero(ws.slots, kSlotArrayBytes, s)) !=
                          hipSuccess)
             return device_error(e, "clear slots");
         if (n > 1 && (e = launch_init_full(A, lda, n, ws.W[0], ws.ldw, s)) != hipSuccess)
@@ -475,7 +475,7 @@ extern "C" int skltlt_pfaffian_partial(int n, const double *A, int lda, double *
         hipError_t e = launch_set_int(ipiv, 0, s);
         if (e != hipSuccess)
             return device_error(e, "set ipiv[0]");
-        if (n > 1 && (e = launch_fill_zero(ws.slots, (size_t)kSlotBytes * 2 * kSlotsPerParity, s)) !=
+        if (n > 1 && (e = launch_fill_zero(ws.slots, kSlotArrayBytes, s)) !=
                          hipSuccess)
             return device_error(e, "clear slots");
         if (n > 1 && (e = launch_init_full(A, lda, n, ws.W[0], ws.ldw, s)) != hipSuccess)

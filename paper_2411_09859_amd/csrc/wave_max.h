@@ -15,34 +15,39 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// One step of a 32-bit unsigned max over lanes with a DPP data movement
-// (row_mask selects the rows that take the moved value; others keep theirs).
-template <int CTRL, int ROWS>
-__device__ __forceinline__ unsigned dpp_max_u32(unsigned x)
-{
-    const unsigned o = (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, ROWS, 0xf, false);
-    return (o > x) ? o : x;
-}
-
 // Largest value over lanes 0 .. CL-1 (CL = 16, 32 or 64), as a uniform
 // value: pairs and quads (quad_perm), 8 and 16 lanes (row half mirror, row
 // mirror), then lane 15 of each row into the next and lane 31 into the upper
-// half (row_bcast 15 / 31), the maximum ending in lane 0 (CL = 16), 31 or
-// 63.  All VALU, no LDS.
+// half (row_bcast 15 / 31 with row masks), the maximum ending in lane 15
+// (CL = 16), 31 or 63.  Each step is one v_max_u32 whose first operand is
+// the DPP-moved register, x = max(x[moved], x); rows outside the row mask,
+// and lanes without a source lane, keep x.  A DPP read of a register written
+// by the previous VALU instruction needs two wait states (the s_nop 1s).
+// All VALU, no LDS.
 template <int CL>
 __device__ __forceinline__ unsigned lanes_max_u32(unsigned x)
 {
     static_assert(CL == 16 || CL == 32 || CL == 64, "lane count");
-    x = dpp_max_u32<0xb1, 0xf>(x);
-    x = dpp_max_u32<0x4e, 0xf>(x);
-    x = dpp_max_u32<0x141, 0xf>(x);
-    x = dpp_max_u32<0x140, 0xf>(x);
+    asm volatile("s_nop 1\n\t"
+                 "v_max_u32_dpp %0, %0, %0 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1\n\t"
+                 "v_max_u32_dpp %0, %0, %0 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1\n\t"
+                 "v_max_u32_dpp %0, %0, %0 row_half_mirror row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1\n\t"
+                 "v_max_u32_dpp %0, %0, %0 row_mirror row_mask:0xf bank_mask:0xf\n\t"
+                 "s_nop 1"
+                 : "+v"(x));
     if constexpr (CL == 16)
-        return (unsigned)__builtin_amdgcn_readlane((int)x, 0);
-    x = dpp_max_u32<0x142, 0xa>(x);
+        return (unsigned)__builtin_amdgcn_readlane((int)x, 15);
+    asm volatile("v_max_u32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+                 "s_nop 1"
+                 : "+v"(x));
     if constexpr (CL == 32)
         return (unsigned)__builtin_amdgcn_readlane((int)x, 31);
-    x = dpp_max_u32<0x143, 0xc>(x);
+    asm volatile("v_max_u32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+                 "s_nop 1"
+                 : "+v"(x));
     return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
 }
 
