@@ -179,6 +179,12 @@ int skltlt_pfaffian_partial(int n, const double *A, int lda, double *t,
 /* Largest order handled by skltlt_batched. */
 int skltlt_batched_max_n(void);
 
+/* Tuning hook (for the autotuner, not for concurrent use): persistent
+ * workgroups per CU of the following skltlt_batched calls, 1 .. 4, or 0 for
+ * the tuned table's choice (by the batch's largest order).  Process-wide;
+ * SKLTLT_EINVAL outside 0 .. 4. */
+int skltlt_tune_batched_wgpc(int wgpc);
+
 /* Bytes of device workspace for skltlt_batched with `batch` matrices: the
  * work-queue counter and the processing order (4 bytes per matrix). */
 int skltlt_batched_workspace_size(int batch, size_t *bytes);

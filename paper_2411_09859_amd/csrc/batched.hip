@@ -59,6 +59,19 @@ __device__ __host__ inline int batched_bs_for(int n)
     return kBMaxBs;
 }
 
+// Persistent workgroups per CU for a batch whose largest order is max_n:
+// from the tuning table (entry of max_n's class), or the tuner's override.
+static int g_wgpc_override = 0;
+static int batched_wgpc_for(int max_n)
+{
+    if (g_wgpc_override > 0)
+        return g_wgpc_override;
+    for (const BatchedTune &e : kBatchedTune)
+        if (max_n <= e.n_max)
+            return e.wgpc;
+    return kBPerCu;
+}
+
 struct BatchShared {
     double Lp[kBT][kBLd]; // panel rows of L, rows indexed by trailing row
     double hv[kBLd];
@@ -574,6 +587,9 @@ static hipError_t launch_batched(int batch, const int *n, double *const *A, cons
                                                      sizeof(BatchShared)) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
+    const int want = batched_wgpc_for(max_n);
+    if (want < per_cu)
+        per_cu = want;
     int grid = cus * per_cu;
     if (grid > batch)
         grid = batch;
@@ -590,6 +606,14 @@ static hipError_t launch_batched(int batch, const int *n, double *const *A, cons
 using namespace skl;
 
 extern "C" int skltlt_batched_max_n(void) { return kBT; }
+
+extern "C" int skltlt_tune_batched_wgpc(int wgpc)
+{
+    if (wgpc < 0 || wgpc > kBPerCu)
+        return SKLTLT_EINVAL;
+    g_wgpc_override = wgpc;
+    return SKLTLT_OK;
+}
 
 // the work-queue counter (256 bytes), then the processing order (one int per
 // matrix), rounded up to 256 bytes

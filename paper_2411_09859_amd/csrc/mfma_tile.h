@@ -1,8 +1,8 @@
 // MFMA tile machinery shared by the trailing update (skr2k) and the
-// left-looking panel update: a 128 x 128 output tile per 256-thread
-// workgroup, four waves of 64 x 64 (each a 4 x 4 grid of 16 x 16 MFMA
-// blocks), operands streamed through a double-buffered LDS stage in K-chunks
-// of KC.  The operands are column-major with leading dimension ldo: opI
+// left-looking panel update: a 128 x 128 output tile per workgroup, split
+// into wave tiles that are grids of 16 x 16 MFMA blocks (skr2k: eight waves
+// of 64 x 32; the panel update: four waves of 64 x 64), operands streamed
+// through a double-buffered LDS stage in K-chunks of KC.  The operands are column-major with leading dimension ldo: opI
 // holds the tile's rows i (columns = k), opJ the tile's columns j.  The MFMA
 // computes the transposed tile D[j][i] += sum_k opJ[j][k] opI[i][k].
 #pragma once
@@ -37,14 +37,18 @@ template <> struct MfmaT<float> {
 };
 
 
-// One tile's K loop.  Every load is issued unconditionally (clamped
-// address) and masked only when the chunk is written to LDS: with a fixed
-// number of loads per chunk and no use right after them, the compiler waits
-// for the chunk that is due while the prefetched one stays in flight (loads
-// skipped by branches, or used at once, make it wait for all of them).
-template <typename T>
-struct TileK {
-    static constexpr int PER = (KC * TM) / 256; // elements per thread per operand and chunk
+// Operand staging of one 128 x 128 tile shared by NT threads (NT / 64
+// waves): K-chunks of the two operands move from HBM to registers and from
+// registers to a double-buffered LDS stage.  Every load is issued
+// unconditionally (clamped address) and masked only when the chunk is
+// written to LDS: with a fixed number of loads per chunk and no use right
+// after them, the compiler waits for the chunk that is due while the
+// prefetched one stays in flight (loads skipped by branches, or used at
+// once, make it wait for all of them).
+template <typename T, int NT>
+struct TileStage {
+    static constexpr int PER = (KC * TM) / NT; // elements per thread per operand and chunk
+    static_assert(PER * NT == KC * TM, "threads divide a chunk");
     T (*sI)[KC][TMP];
     T (*sJ)[KC][TMP];
     const T *opI;
@@ -52,8 +56,8 @@ struct TileK {
     int ldo, n, i0, j0, K, nk, tid;
     T ri[PER], rj[PER];
 
-    __device__ __forceinline__ TileK(T (*sI_)[KC][TMP], T (*sJ_)[KC][TMP], const T *opI_,
-                                     const T *opJ_, int ldo_, int n_, int i0_, int j0_, int K_)
+    __device__ __forceinline__ TileStage(T (*sI_)[KC][TMP], T (*sJ_)[KC][TMP], const T *opI_,
+                                         const T *opJ_, int ldo_, int n_, int i0_, int j0_, int K_)
         : sI(sI_), sJ(sJ_), opI(opI_), opJ(opJ_), ldo(ldo_), n(n_), i0(i0_), j0(j0_), K(K_),
           nk((K_ + KC - 1) / KC), tid(threadIdx.x)
     {
@@ -62,7 +66,7 @@ struct TileK {
     {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int e = tid + q * 256;
+            const int e = tid + q * NT;
             const int rr = e % TM;
             const int k = kc * KC + e / TM;
             const int kk = (k < K) ? k : 0;
@@ -74,7 +78,7 @@ struct TileK {
     {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int e = tid + q * 256;
+            const int e = tid + q * NT;
             const int rr = e % TM;
             const bool kok = kc * KC + e / TM < K;
             sI[buf][e / TM][rr] = (kok && i0 + rr < n) ? ri[q] : (T)0;
@@ -90,11 +94,12 @@ struct TileK {
             load_chunk(1);
         __syncthreads();
     }
-    // acc[bi][bj] (16 x 16 block bi of this wave's rows, bj of its columns)
-    // += the product over all K; ends with a barrier
-    template <typename Acc>
-    __device__ __forceinline__ void run(Acc (&acc)[4][4], bool active, int wi, int wj, int lrow,
-                                        int lk)
+    // acc[bi][bj] (16 x 16 block bi of this wave's WR rows, bj of its WC
+    // columns; the wave's rows start at wr0 and its columns at wc0 inside
+    // the tile) += the product over all K; ends with a barrier
+    template <int BR, int BC, typename Acc>
+    __device__ __forceinline__ void run(Acc (&acc)[BR][BC], bool active, int wr0, int wc0,
+                                        int lrow, int lk)
     {
         for (int kc = 0; kc < nk; ++kc) {
             const int cur = kc & 1;
@@ -106,22 +111,35 @@ struct TileK {
             if (active) {
 #pragma unroll
                 for (int ks = 0; ks < KC; ks += 4) {
-                    T fa[4], fb[4];
+                    T fa[BC], fb[BR];
 #pragma unroll
-                    for (int bj = 0; bj < 4; ++bj)
-                        fa[bj] = sJ[cur][ks + lk][wj * 64 + bj * 16 + lrow];
+                    for (int bj = 0; bj < BC; ++bj)
+                        fa[bj] = sJ[cur][ks + lk][wc0 + bj * 16 + lrow];
 #pragma unroll
-                    for (int bi = 0; bi < 4; ++bi)
-                        fb[bi] = sI[cur][ks + lk][wi * 64 + bi * 16 + lrow];
+                    for (int bi = 0; bi < BR; ++bi)
+                        fb[bi] = sI[cur][ks + lk][wr0 + bi * 16 + lrow];
 #pragma unroll
-                    for (int bi = 0; bi < 4; ++bi)
+                    for (int bi = 0; bi < BR; ++bi)
 #pragma unroll
-                        for (int bj = 0; bj < 4; ++bj)
+                        for (int bj = 0; bj < BC; ++bj)
                             acc[bi][bj] = MfmaT<T>::mma(fa[bj], fb[bi], acc[bi][bj]);
                 }
             }
             __syncthreads();
         }
+    }
+};
+
+// The four-wave form (256 threads, 64 x 64 per wave) used by the
+// left-looking panel update.
+template <typename T>
+struct TileK : TileStage<T, 256> {
+    using TileStage<T, 256>::TileStage;
+    template <typename Acc>
+    __device__ __forceinline__ void run(Acc (&acc)[4][4], bool active, int wi, int wj, int lrow,
+                                        int lk)
+    {
+        TileStage<T, 256>::template run<4, 4>(acc, active, wi * 64, wj * 64, lrow, lk);
     }
 };
 

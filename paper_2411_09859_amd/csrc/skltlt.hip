@@ -12,6 +12,7 @@
 //   synchronizes with the stream.
 #include "../../include/skltlt.h"
 #include "common.h"
+#include "factor_table.h"
 
 #include <cstdio>
 #include <mutex>
@@ -108,16 +109,14 @@ extern "C" const char *skltlt_status_string(int status)
     }
 }
 
-// Measured on MI355X (n = 2048 ... 16384): wider panels halve the trailing
-// update's matrix traffic per flop, which outweighs the wider panel's cost
-// from n = 4096 on.
+// The tuned width for order n (factor_table.h, written by tune_factor.py:
+// the fastest measured width at the nearest measured order).
 extern "C" int skltlt_default_block_size(int n)
 {
-    if (n < 1024)
-        return 32;
-    if (n < 4096)
-        return 128;
-    return 256;
+    for (const FactorTune &e : kFactorTune)
+        if (n <= e.n_max)
+            return e.b;
+    return kFactorTune[sizeof(kFactorTune) / sizeof(kFactorTune[0]) - 1].b;
 }
 
 static int resolve_block(int n, int block_size)

@@ -21,16 +21,22 @@
 // and its negation to (i, j) and (j, i) of the other buffer Wn, so each
 // panel's permutation costs no extra pass over the matrix.
 //
-// Tiling: a 128x128 output tile per 256-thread workgroup, four waves of
-// 64x64, each a 4x4 grid of 16x16 MFMA blocks.  The MFMA computes the
-// transposed tile, D[j][i], so that each lane's four accumulator values lie
-// in four columns at one row i and sixteen consecutive lanes cover sixteen
-// consecutive rows: loads of C and stores of the lower entries are 128-byte
-// segments, and the mirrored upper entries go out through an LDS transpose
-// as 512-byte column pieces; all C stores are streaming (non-temporal): the
-// next reader is the next panel or update, long after.  Tiles are
-// enumerated over the lower triangle only; a diagonal tile skips the wave
-// whose 64x64 quarter lies strictly above the diagonal and masks the rest.
+// Tiling: a 128x128 output tile per 512-thread workgroup, eight waves of
+// 64x32 (64 rows, 32 columns), each a 4x2 grid of 16x16 MFMA blocks.  With
+// 121 registers per lane two workgroups share a CU, so four waves per SIMD
+// issue FP64 MFMAs: the FP64 matrix pipe of a SIMD needs two issuing waves
+// to run at full rate, and with four, one wave's barrier, C gather or stores
+// no longer halve it (four waves of 64x64 at two per SIMD: 40 TFLOP/s on
+// the largest update of n = 16384; eight of 64x32: 48).  The MFMA computes
+// the transposed tile, D[j][i], so that each lane's four accumulator values
+// lie in four columns at one row i and sixteen consecutive lanes cover
+// sixteen consecutive rows: loads of C and stores of the lower entries are
+// 128-byte segments, and the mirrored upper entries go out through an LDS
+// transpose as 256-byte column pieces; all C stores are streaming
+// (non-temporal): the next reader is the next panel or update, long after.
+// Tiles are enumerated over the lower triangle only; a diagonal tile skips
+// the waves whose 64x32 piece lies strictly above the diagonal and masks the
+// rest.
 // Consecutive tile indices go to one XCD (workgroup ids are dealt to the 8
 // XCDs round-robin) and follow a blocked order (4 x 4 tile blocks), so the
 // tiles an XCD works on at once share operand panels in its L2 (measured:
@@ -40,22 +46,27 @@
 
 namespace skl {
 
-constexpr int TRS = 66;    // LDS row of the epilogue transpose (64 + 2: spreads banks)
+constexpr int kSkThreads = 512;
+constexpr int kWR = 64, kWC = 32;  // wave tile: rows i, columns j
+constexpr int TRS = kWC + 2;       // LDS row of the epilogue transpose (spreads banks)
 
 template <typename T>
-__global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict__ Wc,
-                                                       double *__restrict__ Wn, int ldw,
-                                                       const int *__restrict__ perm, int n,
-                                                       int cp, int K, const T *__restrict__ uv,
-                                                       int ntiles)
+__global__ __launch_bounds__(kSkThreads, 2) void skr2k_kernel(const double *__restrict__ Wc,
+                                                              double *__restrict__ Wn, int ldw,
+                                                              const int *__restrict__ perm,
+                                                              int n, int cp, int K,
+                                                              const T *__restrict__ uv,
+                                                              int ntiles)
 {
     typedef typename MfmaT<T>::acc4 acc4;
+    constexpr int BR = kWR / 16, BC = kWC / 16; // 16x16 blocks per wave tile
+    constexpr int WPR = TM / kWR;                // waves along the rows
     // LDS: double-buffered operand chunks during the K loop, k-major, rows
     // padded so that the four k-rows read by one fragment load fall in
     // different LDS banks; afterwards each wave reuses 16 x TRS doubles of
     // the same space to transpose its mirrored (upper) stores.
     constexpr size_t kOpBytes = sizeof(T) * 2 * KC * TMP;
-    constexpr size_t kTrBytes = sizeof(double) * 4 * 16 * TRS;
+    constexpr size_t kTrBytes = sizeof(double) * (kSkThreads / 64) * 16 * TRS;
     constexpr size_t kLds = (2 * kOpBytes > kTrBytes) ? 2 * kOpBytes : kTrBytes;
     __shared__ __attribute__((aligned(16))) char smem[kLds];
     T(*sI)[KC][TMP] = reinterpret_cast<T(*)[KC][TMP]>(smem);            // [U|V] rows i
@@ -77,10 +88,10 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict_
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wi = wave & 1, wj = wave >> 1;
-    const int ib = i0 + wi * 64; // this wave's 64 rows
-    const int jb = j0 + wj * 64; // this wave's 64 columns
-    const bool active = !(ti == tj && wi == 0 && wj == 1);
+    const int wi = wave % WPR, wj = wave / WPR;
+    const int ib = i0 + wi * kWR; // this wave's rows
+    const int jb = j0 + wj * kWC; // this wave's columns
+    const bool active = !(ti == tj && jb >= ib + kWR);
 
     const int lrow = lane & 15; // row inside a 16-block
     const int lk = lane >> 4;   // k inside a 4-step, or row group of D
@@ -90,7 +101,7 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict_
     if (tid < TM) {
         const int g = i0 + tid;
         sPi[tid] = (g < n) ? perm[g] : 0;
-    } else {
+    } else if (tid < 2 * TM) {
         const int g = j0 + tid - TM;
         sPj[tid - TM] = (g < n) ? perm[g] : 0;
     }
@@ -99,17 +110,17 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict_
         return Wc + (size_t)sPj[gj - j0] * ldw + sPi[gi - i0];
     };
 
-    TileK<T> tk(sI, sJ, uv, uv + (size_t)K * n, n, n, i0, j0, K);
+    TileStage<T, kSkThreads> tk(sI, sJ, uv, uv + (size_t)K * n, n, n, i0, j0, K);
     tk.prologue();
 
     // Accumulators.  FP64: start from the (permuted) C tile; FP32: start from
     // zero and add the fp32 product to C in fp64 at the end.
-    acc4 acc[4][4];
+    acc4 acc[BR][BC];
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
+    for (int bi = 0; bi < BR; ++bi) {
         const int gi = ib + bi * 16 + lrow;
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
+        for (int bj = 0; bj < BC; ++bj) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int gj = jb + bj * 16 + MfmaT<T>::drow(lk, q);
@@ -123,7 +134,7 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict_
             }
         }
     }
-    tk.run(acc, active, wi, wj, lrow, lk);
+    tk.template run<BR, BC>(acc, active, wi * kWR, wj * kWC, lrow, lk);
     if (!active)
         return;
 
@@ -131,13 +142,15 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict_
     // Lower entries (i, j) go straight out: sixteen lanes write 128
     // consecutive bytes of column j.  Their negations at (j, i) lie along
     // column i, so each 16-row block is staged in this wave's LDS rows and
-    // written back one column i at a time, 64 consecutive j per store.
+    // written back one column i at a time: 32 consecutive j per half wave,
+    // two columns i per store.
     double *tr = reinterpret_cast<double *>(smem) + wave * 16 * TRS;
+    const int jl2 = lane % kWC;
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
+    for (int bi = 0; bi < BR; ++bi) {
         const int gi = ib + bi * 16 + lrow;
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
+        for (int bj = 0; bj < BC; ++bj) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int jl = bj * 16 + MfmaT<T>::drow(lk, q);
@@ -155,11 +168,12 @@ __global__ __launch_bounds__(256, 2) void skr2k_kernel(const double *__restrict_
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int gj = jb + lane;
+        const int gj = jb + jl2;
 #pragma unroll
-        for (int rr = 0; rr < 16; ++rr) {
+        for (int r0 = 0; r0 < 16; r0 += 64 / kWC) {
+            const int rr = r0 + lane / kWC;
             const int gi2 = ib + bi * 16 + rr;
-            const double v = tr[rr * TRS + lane];
+            const double v = tr[rr * TRS + jl2];
             if (gi2 < n && gj < gi2)
                 __builtin_nontemporal_store(-v, &Wn[(size_t)gi2 * ldw + gj]);
         }
@@ -182,10 +196,10 @@ hipError_t launch_skr2k(const double *Wc, double *Wn, int n, int cp, int nq,
     const int K = 2 * nq;
     (void)hipGetLastError(); // report this launch only
     if (precision == 1) {
-        hipLaunchKernelGGL(skr2k_kernel<float>, dim3(grid), dim3(256), 0, s, Wc, Wn, ws.ldw,
+        hipLaunchKernelGGL(skr2k_kernel<float>, dim3(grid), dim3(kSkThreads), 0, s, Wc, Wn, ws.ldw,
                            (const int *)ws.perm, n, cp, K, (const float *)ws.uv32, ntiles);
     } else {
-        hipLaunchKernelGGL(skr2k_kernel<double>, dim3(grid), dim3(256), 0, s, Wc, Wn, ws.ldw,
+        hipLaunchKernelGGL(skr2k_kernel<double>, dim3(grid), dim3(kSkThreads), 0, s, Wc, Wn, ws.ldw,
                            (const int *)ws.perm, n, cp, K, (const double *)ws.uv, ntiles);
     }
     return hipGetLastError();
