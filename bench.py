@@ -89,6 +89,7 @@ def panel_flops(n, b):
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "skr2k_n16384_b256_traffic.txt")
+PANEL_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "panel_n16384_b256_traffic.txt")
 MFMA_SUMMARY = os.path.join(ROOT, "profiles", "skr2k_n16384_b256_mfma_counters.txt")
 
 
@@ -111,6 +112,26 @@ def _committed_counters(path, n, b, key):
 def measured_traffic(n, b):
     """Counter-measured HBM bytes per skr2k launch from the committed summary."""
     return _committed_counters(TRAFFIC_SUMMARY, n, b, "traffic_bytes_per_launch")
+
+
+def measured_panel_traffic(n, b):
+    """Counter-measured HBM bytes per panel launch from the committed summary."""
+    return _committed_counters(PANEL_TRAFFIC_SUMMARY, n, b, "traffic_bytes_per_launch")
+
+
+def panel_bytes(n, b):
+    """Algorithmic HBM bytes of all panel launches of one factorization: the
+    new column of every trailing row at each step, the panel's columns of L
+    and the operands U, V written once."""
+    tot = 0.0
+    k0 = 0
+    while k0 < n - 1:
+        nb = min(b, n - 1 - k0)
+        m = n - k0 - 1
+        cp = k0 + nb
+        tot += 16.0 * m * nb + (16.0 * (n - cp) * ((nb + 1) // 2) if cp < n - 1 else 0.0)
+        k0 = cp
+    return tot
 
 
 def measured_mfma_busy(n, b):
@@ -674,10 +695,16 @@ def main():
         panel = {"ms_per_step": pms, "us_per_column_step": us_col,
                  "alu_flops": pf, "alu_tflops": pf / (pms * 1e-3) / 1e12,
                  "alu_frac": pf / (pms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+        ptraffic, ptraffic_src = measured_panel_traffic(n, b)
+        palg = panel_bytes(n, b) / launches
         roofs["panel"] = {
             "kernel": f"panel_kernel<512,{panel_tpr(b)},65>", "bound": "alu",
             "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": ptraffic,
+            "traffic_source": ptraffic_src,
+            "traffic_over_algorithmic": (ptraffic / palg) if ptraffic else None,
+            "algorithmic_bytes_per_launch": palg,
+            "hbm_gbs_algorithmic": palg / (per_launch_ms * 1e-3) / 1e9,
             "flops_per_launch": pf / launches, "launches": launches,
             "avg_launch_ms": per_launch_ms,
             "latency": {"us_per_column_step": us_col, "budget_us_per_column_step": 2.0,
