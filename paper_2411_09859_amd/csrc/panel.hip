@@ -117,6 +117,43 @@ __device__ __forceinline__ void st_xcd(double *p, double v, bool local)
 // Wait until this wave's outstanding memory operations have completed.
 __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Stores into the row-major mirror of L through a bounds-checked buffer
+// resource.  Every thread issues both forms of the store of a step, plain
+// and device scope, and passes the end of the buffer as the offset of the
+// one it does not use (or of both, with nothing to store), which the
+// hardware drops.  So each step issues the same memory instructions on
+// every path, and the compiler's waits for the step's earlier loads do not
+// have to cover the later ones (with a store issued on some paths only, its
+// wait for the mirror loads also waited for the next column's HBM load).
+struct MirrorIO {
+    __amdgpu_buffer_rsrc_t rs;
+    int nrec;   // bytes covered; an offset of nrec is out of range
+    bool local; // plain stores (every working group on this XCD)
+
+    // bytes < 2^31 (the supported orders, n <= 2^18, keep the mirror below
+    // 0.6 GB); readfirstlane keeps the
+    // resource in scalar registers (a resource the compiler cannot prove
+    // uniform is applied lane by lane in a loop)
+    __device__ __forceinline__ MirrorIO(double *mirror, int bytes, bool local_)
+        : nrec(__builtin_amdgcn_readfirstlane(bytes)), local(local_)
+    {
+        rs = __builtin_amdgcn_make_buffer_rsrc((void *)mirror, (short)0, nrec, 0x00020000);
+    }
+    // entry (row, col) when on, else nothing
+    __device__ __forceinline__ void store(bool on, int row, int ldm, int col, double v) const
+    {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        u32x2 d;
+        d.x = (unsigned)b;
+        d.y = (unsigned)(b >> 32);
+        const int off = (row * ldm + col) * (int)sizeof(double);
+        __builtin_amdgcn_raw_buffer_store_b64(d, rs, (on && local) ? off : nrec, 0, 0);
+        // device scope (sc1)
+        __builtin_amdgcn_raw_buffer_store_b64(d, rs, (on && !local) ? off : nrec, 0, 16);
+    }
+};
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // The pivot exchange between groups.  A slot is one 16-byte access.  Each
@@ -435,7 +472,9 @@ __device__ __forceinline__ bool groups_share_xcd(Slot *slots, int G, int w, int 
             same = all ? 1 : 0;
     }
     __syncthreads();
-    return same != 0;
+    // the same value in every lane; readfirstlane lets the compiler branch
+    // on it with scalar branches
+    return __builtin_amdgcn_readfirstlane(same) != 0;
 }
 
 template <int NT, int TPR, int kNS>
@@ -544,6 +583,10 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     // the carried column's mirror entry
     if (multi && exists && sub == 0)
         st_xcd(&mirror[(size_t)phys * ldm], Lnew[0], local);
+    const MirrorIO mio(mirror, (int)sizeof(double) * G * R * ldm, local);
+    // nothing in flight when the steps begin (a load still pending from here
+    // would make the compiler wait for every load at each step's start)
+    wait_vm();
 
     for (int j = 0; j < nb; ++j) {
         const int c = k0 + j;
@@ -670,23 +713,24 @@ __global__ __launch_bounds__(NT) void panel_kernel(
         //     new group, the finished one is flushed first (every thread).
         //     Its mirror store is issued while the loads above are in
         //     flight, so it has completed sooner when the next step's
-        //     publication waits for it.
+        //     publication waits for it; every thread issues it (see
+        //     MirrorIO), so the next column's load stays in flight past the
+        //     waits for the mirror loads and the barrier ending the step,
+        //     until the next step's products are formed.
         const int a1 = j + 1;
         if (((a1 / TPR) / kRing) != gr)
             flush_ring(gr);
-        if (exists && pos >= r) {
-            const double l = (pos == r) ? 1.0 : ((tau != 0.0) ? xv / tau : 0.0);
-            if (sub == a1 % TPR) {
-                // select into the ring (keeps it in registers: an indexed
-                // store would move the array to scratch memory)
-                const int slot = (a1 / TPR) % kRing;
+        const bool lrow_on = exists && pos >= r && sub == a1 % TPR;
+        const double l = (pos == r) ? 1.0 : ((tau != 0.0) ? xv / tau : 0.0);
+        if (lrow_on) {
+            // select into the ring (keeps it in registers: an indexed
+            // store would move the array to scratch memory)
+            const int slot = (a1 / TPR) % kRing;
 #pragma unroll
-                for (int i = 0; i < kRing; ++i)
-                    Lnew[i] = (i == slot) ? l : Lnew[i];
-                if (multi && pos > r)
-                    st_xcd(&mirror[(size_t)phys * ldm + a1], l, local);
-            }
+            for (int i = 0; i < kRing; ++i)
+                Lnew[i] = (i == slot) ? l : Lnew[i];
         }
+        mio.store(multi && lrow_on && pos > r, phys, ldm, a1, l);
 
         // 5e. with several groups, thread a forms h[a] of the next step from
         //     the mirror entries and t.
