@@ -981,7 +981,10 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
             pv.bc_fail = 1;
     }
     const SlotIO sio(slots, base, local);
+    const MirrorIO mio(mirror, (int)sizeof(double) * G * R * ldm, local);
     const double qnan = __longlong_as_double(0x7ff8000000000000ll);
+    // nothing in flight when the pairs begin
+    wait_vm();
 
     const int npair = nb / 2;
     for (int i = 0; i < npair; ++i) {
@@ -1023,41 +1026,41 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
         }
         const bool nxt = (i + 1 < npair); // column c+2 belongs to this panel
         const int physE = (p == c + 2) ? physR0 : physE0; // row holding label c+2
-        double yo = 0.0, ye = 0.0; // every thread of a row loads (one address)
-        if (exists && pos > r)
-            yo = W[(size_t)(base + physp) * ldw + orow];
-        if (nxt && exists && pos > c + 2)
-            ye = W[(size_t)(base + physE) * ldw + orow];
         const int a = tid;
         const bool ha = (a < 2 * i);
-        double mp1 = 0.0, me0 = 0.0, me1 = 0.0, wsc = 0.0;
-        if (ha) {
-            mp1 = ld_dev(&mirror[(size_t)physp * ldm + (a ^ 1)]);
-            if (nxt) {
-                me0 = ld_dev(&mirror[(size_t)physE * ldm + a]);
-                me1 = ld_dev(&mirror[(size_t)physE * ldm + (a ^ 1)]);
-            }
-        }
-        // entries (label c+2, label r) and (label c+2, label c) of Y
-        if (nxt && a == 2 * i)
-            wsc = W[(size_t)(base + physp) * ldw + base + physE];
-        if (nxt && a == 2 * i + 1)
-            wsc = W[(size_t)origC * ldw + base + physE];
+        // Every thread issues every load of the pair, in the order of their
+        // use, at addresses kept in range (rows and columns named by the
+        // window always exist); what a thread does not need is discarded
+        // where the value is used.  A load issued on some paths only makes
+        // the compiler's waits for the earlier ones also cover the later
+        // ones: the next column's HBM load then sat before the pair's
+        // barriers.  Order: the pivot row's and the label-(c+2) row's mirror
+        // entries (for h of the second column and the dot products), the
+        // second column (every thread of a row loads, one address), entries
+        // (label c+2, label r) or (label c+2, label c) of Y, and last the
+        // next pair's first column.
+        const int ac = ha ? a : 0;
+        const double mp1 = ld_dev(&mirror[(size_t)physp * ldm + (ac ^ 1)]);
+        const double me0 = ld_dev(&mirror[(size_t)physE * ldm + ac]);
+        const double me1 = ld_dev(&mirror[(size_t)physE * ldm + (ac ^ 1)]);
+        const int yrow = exists ? orow : base;
+        const double yo = W[(size_t)(base + physp) * ldw + yrow];
+        const double wsc = W[(size_t)((a == 2 * i + 1) ? origC : base + physp) * ldw + base + physE];
+        const double ye = W[(size_t)(base + physE) * ldw + yrow];
 
         // 3a. l_i for the rows below r
         const bool below = exists && pos > r;
         const double lval = below ? ((tau != 0.0) ? xv / tau : 0.0) : 0.0;
         insert(2 * i, lval, below);
-        if (below && sub == (2 * i) % TPR)
-            st_xcd(&mirror[(size_t)phys * ldm + 2 * i], lval, local);
+        mio.store(below && sub == (2 * i) % TPR, phys, ldm, 2 * i, lval);
         // h of the second column (pivot row entries) and the two dot
         // products of the label-(c+2) row with h_c and h_r
         const double hoa = ha ? ((a & 1) ? mp1 : -mp1) : 0.0;
-        const double hea = ha ? ((a & 1) ? me1 : -me1) : 0.0;
+        const double hea = (ha && nxt) ? ((a & 1) ? me1 : -me1) : 0.0;
         double dk = 0.0, dob = 0.0;
         if (a < NA) {
             ho[a] = hoa;
-            if (ha) {
+            if (ha && nxt) {
                 dk = me0 * hv[a];
                 dob = me0 * hoa;
             }
@@ -1074,11 +1077,11 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
         __syncthreads();
 
         // 3b. the pair's second column and c_i
-        ycol = yo;
-        const double xo = gemv(ho, ycol);
+        // (rows that are not below r load a value they do not use: their xo
+        // is discarded)
+        const double xo = gemv(ho, yo);
         insert(2 * i + 1, below ? xo : 0.0, below);
-        if (below && sub == (2 * i + 1) % TPR)
-            st_xcd(&mirror[(size_t)phys * ldm + 2 * i + 1], xo, local);
+        mio.store(below && sub == (2 * i + 1) % TPR, phys, ldm, 2 * i + 1, xo);
 
         // 4. h of column c+2: earlier pairs from the fetched row; this
         //    pair's c_i and l_i at label c+2 recomputed from the same data
@@ -1100,6 +1103,8 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
             }
             hv[a] = hn;
         }
+        // the next pair's candidates all have labels above c+2, for which
+        // ye is their entry; the other rows' x is never used
         ycol = ye;
         if (tid == 0) {
             tl[i] = tau;
