@@ -185,6 +185,14 @@ int skltlt_batched_max_n(void);
  * SKLTLT_EINVAL outside 0 .. 4. */
 int skltlt_tune_batched_wgpc(int wgpc);
 
+/* Tuning hook (for measurements, not for concurrent use): the trailing
+ * update of skltlt_factor / skltlt_pfaffian takes 64 x 64 tiles instead of
+ * 128 x 128 when its trailing block has fewer than `tiles` 128-tiles (lower
+ * triangle, diagonal included); 0 never, negative restores the default (the
+ * device's CU count).  Both tilings give bit-identical results.
+ * Process-wide; always SKLTLT_OK. */
+int skltlt_tune_skr2k_small_tiles(int tiles);
+
 /* Bytes of device workspace for skltlt_batched with `batch` matrices: the
  * work-queue counter and the processing order (4 bytes per matrix). */
 int skltlt_batched_workspace_size(int batch, size_t *bytes);

@@ -74,6 +74,8 @@ def lib():
         L.skltlt_batched_max_n.restype = i
         L.skltlt_tune_batched_wgpc.argtypes = [i]
         L.skltlt_tune_batched_wgpc.restype = i
+        L.skltlt_tune_skr2k_small_tiles.argtypes = [i]
+        L.skltlt_tune_skr2k_small_tiles.restype = i
         L.skltlt_batched_workspace_size.argtypes = [i, ctypes.POINTER(sz)]
         L.skltlt_batched_workspace_size.restype = i
         L.skltlt_batched.argtypes = [i, vp, vp, vp, vp, vp, vp, vp, vp, i, i, i, vp, sz, vp]

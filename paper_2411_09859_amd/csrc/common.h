@@ -88,6 +88,7 @@ hipError_t launch_lkupd(double *W, int ldw, int n, int c0, int nb, const double 
                         const double *opJ, int ldo, int K, hipStream_t s);
 
 // Wn[i][j] = Wc[perm[i]][perm[j]] - (U V^T - V U^T)[i][j] for i != j >= cp.
+void skr2k_set_small_tiles(int t);
 hipError_t launch_skr2k(const double *Wc, double *Wn, int n, int cp, int nq,
                         const FactorWs &ws, int precision, hipStream_t s);
 

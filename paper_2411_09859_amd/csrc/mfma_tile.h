@@ -37,26 +37,27 @@ template <> struct MfmaT<float> {
 };
 
 
-// Operand staging of one 128 x 128 tile shared by NT threads (NT / 64
-// waves): K-chunks of the two operands move from HBM to registers and from
-// registers to a double-buffered LDS stage.  Every load is issued
+// Operand staging of one TMV x TMV tile (128 unless stated; LDS rows padded
+// to TMPV) shared by NT threads (NT / 64 waves): K-chunks of the two
+// operands move from HBM to registers and from registers to a
+// double-buffered LDS stage.  Every load is issued
 // unconditionally (clamped address) and masked only when the chunk is
 // written to LDS: with a fixed number of loads per chunk and no use right
 // after them, the compiler waits for the chunk that is due while the
 // prefetched one stays in flight (loads skipped by branches, or used at
 // once, make it wait for all of them).
-template <typename T, int NT>
+template <typename T, int NT, int TMV = TM, int TMPV = TMP>
 struct TileStage {
-    static constexpr int PER = (KC * TM) / NT; // elements per thread per operand and chunk
-    static_assert(PER * NT == KC * TM, "threads divide a chunk");
-    T (*sI)[KC][TMP];
-    T (*sJ)[KC][TMP];
+    static constexpr int PER = (KC * TMV) / NT; // elements per thread per operand and chunk
+    static_assert(PER * NT == KC * TMV, "threads divide a chunk");
+    T (*sI)[KC][TMPV];
+    T (*sJ)[KC][TMPV];
     const T *opI;
     const T *opJ;
     int ldo, n, i0, j0, K, nk, tid;
     T ri[PER], rj[PER];
 
-    __device__ __forceinline__ TileStage(T (*sI_)[KC][TMP], T (*sJ_)[KC][TMP], const T *opI_,
+    __device__ __forceinline__ TileStage(T (*sI_)[KC][TMPV], T (*sJ_)[KC][TMPV], const T *opI_,
                                          const T *opJ_, int ldo_, int n_, int i0_, int j0_, int K_)
         : sI(sI_), sJ(sJ_), opI(opI_), opJ(opJ_), ldo(ldo_), n(n_), i0(i0_), j0(j0_), K(K_),
           nk((K_ + KC - 1) / KC), tid(threadIdx.x)
@@ -67,8 +68,8 @@ struct TileStage {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = tid + q * NT;
-            const int rr = e % TM;
-            const int k = kc * KC + e / TM;
+            const int rr = e % TMV;
+            const int k = kc * KC + e / TMV;
             const int kk = (k < K) ? k : 0;
             ri[q] = opI[(size_t)kk * ldo + min(i0 + rr, n - 1)];
             rj[q] = opJ[(size_t)kk * ldo + min(j0 + rr, n - 1)];
@@ -79,10 +80,10 @@ struct TileStage {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = tid + q * NT;
-            const int rr = e % TM;
-            const bool kok = kc * KC + e / TM < K;
-            sI[buf][e / TM][rr] = (kok && i0 + rr < n) ? ri[q] : (T)0;
-            sJ[buf][e / TM][rr] = (kok && j0 + rr < n) ? rj[q] : (T)0;
+            const int rr = e % TMV;
+            const bool kok = kc * KC + e / TMV < K;
+            sI[buf][e / TMV][rr] = (kok && i0 + rr < n) ? ri[q] : (T)0;
+            sJ[buf][e / TMV][rr] = (kok && j0 + rr < n) ? rj[q] : (T)0;
         }
     }
     // the first chunk in LDS, the second in flight

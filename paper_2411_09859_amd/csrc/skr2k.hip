@@ -41,37 +41,41 @@
 // XCDs round-robin) and follow a blocked order (4 x 4 tile blocks), so the
 // tiles an XCD works on at once share operand panels in its L2 (measured:
 // fewer operand re-reads, 6-10 % faster on large trailing blocks).
+// Small trailing blocks (fewer 128-tiles than the chip has CUs, at the end
+// of a factorization) take 64x64 tiles instead: four waves of 32x32 per
+// 256-thread workgroup, so four times as many workgroups share the work.  A
+// 128-tile alone on a CU takes about 52 us whatever the trailing order; the
+// small tiles finish sooner.  Every element is summed over K in the same
+// order by both tilings, so the results are bit for bit the same.
+#include "skltlt.h"
 #include "common.h"
 #include "mfma_tile.h"
 
 namespace skl {
 
-constexpr int kSkThreads = 512;
-constexpr int kWR = 64, kWC = 32;  // wave tile: rows i, columns j
-constexpr int TRS = kWC + 2;       // LDS row of the epilogue transpose (spreads banks)
-
-template <typename T>
-__global__ __launch_bounds__(kSkThreads, 2) void skr2k_kernel(const double *__restrict__ Wc,
-                                                              double *__restrict__ Wn, int ldw,
-                                                              const int *__restrict__ perm,
-                                                              int n, int cp, int K,
-                                                              const T *__restrict__ uv,
-                                                              int ntiles)
+// The update of one output tile of TMV x TMV by NT threads, waves of WR rows
+// by WC columns; TMPV: padded LDS row of the operand stage.
+template <typename T, int TMV, int TMPV, int NT, int WR, int WC>
+__device__ __forceinline__ void skr2k_tile(const double *__restrict__ Wc, double *__restrict__ Wn,
+                                           int ldw, const int *__restrict__ perm, int n, int cp,
+                                           int K, const T *__restrict__ uv, int ntiles)
 {
     typedef typename MfmaT<T>::acc4 acc4;
-    constexpr int BR = kWR / 16, BC = kWC / 16; // 16x16 blocks per wave tile
-    constexpr int WPR = TM / kWR;                // waves along the rows
+    constexpr int BR = WR / 16, BC = WC / 16; // 16x16 blocks per wave tile
+    constexpr int WPR = TMV / WR;             // waves along the rows
+    static_assert(WPR * (TMV / WC) * 64 == NT, "waves cover the tile");
+    constexpr int TRS = WC + 2; // LDS row of the epilogue transpose (spreads banks)
     // LDS: double-buffered operand chunks during the K loop, k-major, rows
     // padded so that the four k-rows read by one fragment load fall in
     // different LDS banks; afterwards each wave reuses 16 x TRS doubles of
     // the same space to transpose its mirrored (upper) stores.
-    constexpr size_t kOpBytes = sizeof(T) * 2 * KC * TMP;
-    constexpr size_t kTrBytes = sizeof(double) * (kSkThreads / 64) * 16 * TRS;
+    constexpr size_t kOpBytes = sizeof(T) * 2 * KC * TMPV;
+    constexpr size_t kTrBytes = sizeof(double) * (NT / 64) * 16 * TRS;
     constexpr size_t kLds = (2 * kOpBytes > kTrBytes) ? 2 * kOpBytes : kTrBytes;
     __shared__ __attribute__((aligned(16))) char smem[kLds];
-    T(*sI)[KC][TMP] = reinterpret_cast<T(*)[KC][TMP]>(smem);            // [U|V] rows i
-    T(*sJ)[KC][TMP] = reinterpret_cast<T(*)[KC][TMP]>(smem + kOpBytes); // [-V|U] rows j
-    __shared__ int sPi[TM], sPj[TM]; // source rows of the tile's rows and columns
+    T(*sI)[KC][TMPV] = reinterpret_cast<T(*)[KC][TMPV]>(smem);            // [U|V] rows i
+    T(*sJ)[KC][TMPV] = reinterpret_cast<T(*)[KC][TMPV]>(smem + kOpBytes); // [-V|U] rows j
+    __shared__ int sPi[TMV], sPj[TMV]; // source rows of the tile's rows and columns
 
     // XCD-grouped tile order
     const int nwg = gridDim.x;
@@ -81,36 +85,38 @@ __global__ __launch_bounds__(kSkThreads, 2) void skr2k_kernel(const double *__re
     if (tau >= ntiles)
         return;
     int ti, tj;
-    tile_of_blocked<4>(tau, (n - cp + TM - 1) / TM, &ti, &tj);
-    const int i0 = cp + ti * TM;
-    const int j0 = cp + tj * TM;
+    tile_of_blocked<4>(tau, (n - cp + TMV - 1) / TMV, &ti, &tj);
+    const int i0 = cp + ti * TMV;
+    const int j0 = cp + tj * TMV;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wi = wave % WPR, wj = wave / WPR;
-    const int ib = i0 + wi * kWR; // this wave's rows
-    const int jb = j0 + wj * kWC; // this wave's columns
-    const bool active = !(ti == tj && jb >= ib + kWR);
+    const int ib = i0 + wi * WR; // this wave's rows
+    const int jb = j0 + wj * WC; // this wave's columns
+    const bool active = !(ti == tj && jb >= ib + WR);
 
     const int lrow = lane & 15; // row inside a 16-block
     const int lk = lane >> 4;   // k inside a 4-step, or row group of D
 
     // Source rows of the tile's rows and columns (loaded first, their latency
     // overlaps the first operand chunk).
-    if (tid < TM) {
-        const int g = i0 + tid;
-        sPi[tid] = (g < n) ? perm[g] : 0;
-    } else if (tid < 2 * TM) {
-        const int g = j0 + tid - TM;
-        sPj[tid - TM] = (g < n) ? perm[g] : 0;
+    for (int q = tid; q < 2 * TMV; q += NT) {
+        if (q < TMV) {
+            const int g = i0 + q;
+            sPi[q] = (g < n) ? perm[g] : 0;
+        } else {
+            const int g = j0 + q - TMV;
+            sPj[q - TMV] = (g < n) ? perm[g] : 0;
+        }
     }
     constexpr bool kF64 = sizeof(T) == 8;
     auto csrc = [&](int gi, int gj) -> const double * {
         return Wc + (size_t)sPj[gj - j0] * ldw + sPi[gi - i0];
     };
 
-    TileStage<T, kSkThreads> tk(sI, sJ, uv, uv + (size_t)K * n, n, n, i0, j0, K);
+    TileStage<T, NT, TMV, TMPV> tk(sI, sJ, uv, uv + (size_t)K * n, n, n, i0, j0, K);
     tk.prologue();
 
     // Accumulators.  FP64: start from the (permuted) C tile; FP32: start from
@@ -134,7 +140,7 @@ __global__ __launch_bounds__(kSkThreads, 2) void skr2k_kernel(const double *__re
             }
         }
     }
-    tk.template run<BR, BC>(acc, active, wi * kWR, wj * kWC, lrow, lk);
+    tk.template run<BR, BC>(acc, active, wi * WR, wj * WC, lrow, lk);
     if (!active)
         return;
 
@@ -142,10 +148,10 @@ __global__ __launch_bounds__(kSkThreads, 2) void skr2k_kernel(const double *__re
     // Lower entries (i, j) go straight out: sixteen lanes write 128
     // consecutive bytes of column j.  Their negations at (j, i) lie along
     // column i, so each 16-row block is staged in this wave's LDS rows and
-    // written back one column i at a time: 32 consecutive j per half wave,
-    // two columns i per store.
+    // written back one column i at a time: WC consecutive j per 64/WC of the
+    // wave, 64/WC columns i per store.
     double *tr = reinterpret_cast<double *>(smem) + wave * 16 * TRS;
-    const int jl2 = lane % kWC;
+    const int jl2 = lane % WC;
 #pragma unroll
     for (int bi = 0; bi < BR; ++bi) {
         const int gi = ib + bi * 16 + lrow;
@@ -170,8 +176,8 @@ __global__ __launch_bounds__(kSkThreads, 2) void skr2k_kernel(const double *__re
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int gj = jb + jl2;
 #pragma unroll
-        for (int r0 = 0; r0 < 16; r0 += 64 / kWC) {
-            const int rr = r0 + lane / kWC;
+        for (int r0 = 0; r0 < 16; r0 += 64 / WC) {
+            const int rr = r0 + lane / WC;
             const int gi2 = ib + bi * 16 + rr;
             const double v = tr[rr * TRS + jl2];
             if (gi2 < n && gj < gi2)
@@ -183,19 +189,60 @@ __global__ __launch_bounds__(kSkThreads, 2) void skr2k_kernel(const double *__re
     }
 }
 
+// 128x128 tiles, eight waves of 64x32, two workgroups per CU
+constexpr int kSkThreads = 512;
+template <typename T>
+__global__ __launch_bounds__(kSkThreads, 2) void skr2k_kernel(const double *__restrict__ Wc,
+                                                              double *__restrict__ Wn, int ldw,
+                                                              const int *__restrict__ perm,
+                                                              int n, int cp, int K,
+                                                              const T *__restrict__ uv,
+                                                              int ntiles)
+{
+    skr2k_tile<T, TM, TMP, kSkThreads, 64, 32>(Wc, Wn, ldw, perm, n, cp, K, uv, ntiles);
+}
+
+// 64x64 tiles (LDS rows padded to 80: k-rows 640 B apart, banks shift by
+// 128 B), four waves of 32x32
+constexpr int kSkSmallThreads = 256;
+constexpr int kSmallTM = 64;
+template <typename T>
+__global__ __launch_bounds__(kSkSmallThreads) void skr2k_small_kernel(
+    const double *__restrict__ Wc, double *__restrict__ Wn, int ldw,
+    const int *__restrict__ perm, int n, int cp, int K, const T *__restrict__ uv, int ntiles)
+{
+    skr2k_tile<T, kSmallTM, 80, kSkSmallThreads, 32, 32>(Wc, Wn, ldw, perm, n, cp, K, uv, ntiles);
+}
+
+// Trailing blocks with fewer 128-tiles than this take the 64x64 tiles.
+static int g_small_tiles = -1;
+
 hipError_t launch_skr2k(const double *Wc, double *Wn, int n, int cp, int nq,
                         const FactorWs &ws, int precision, hipStream_t s)
 {
     const int m = n - cp;
     if (m < 2 || nq <= 0)
         return hipSuccess;
+    if (g_small_tiles < 0)
+        g_small_tiles = device_cu_count();
     const int nt = (m + TM - 1) / TM;
-    const int ntiles = nt * (nt + 1) / 2;
+    const bool small = nt * (nt + 1) / 2 < g_small_tiles;
+    const int ntm = small ? (m + kSmallTM - 1) / kSmallTM : nt;
+    const int ntiles = ntm * (ntm + 1) / 2;
     const int per_xcd = (ntiles + 7) / 8;
     const int grid = per_xcd * 8;
     const int K = 2 * nq;
     (void)hipGetLastError(); // report this launch only
-    if (precision == 1) {
+    if (small) {
+        if (precision == 1)
+            hipLaunchKernelGGL(skr2k_small_kernel<float>, dim3(grid), dim3(kSkSmallThreads), 0, s,
+                               Wc, Wn, ws.ldw, (const int *)ws.perm, n, cp, K,
+                               (const float *)ws.uv32, ntiles);
+        else
+            hipLaunchKernelGGL(skr2k_small_kernel<double>, dim3(grid), dim3(kSkSmallThreads), 0, s,
+                               Wc, Wn, ws.ldw, (const int *)ws.perm, n, cp, K,
+                               (const double *)ws.uv, ntiles);
+    } else if (precision == 1) {
         hipLaunchKernelGGL(skr2k_kernel<float>, dim3(grid), dim3(kSkThreads), 0, s, Wc, Wn, ws.ldw,
                            (const int *)ws.perm, n, cp, K, (const float *)ws.uv32, ntiles);
     } else {
@@ -205,4 +252,14 @@ hipError_t launch_skr2k(const double *Wc, double *Wn, int n, int cp, int nq,
     return hipGetLastError();
 }
 
+// Sets the 128-tile count below which the 64x64 tiles are used (0: never;
+// negative: the default, the device's CU count).
+void skr2k_set_small_tiles(int t) { g_small_tiles = t < 0 ? device_cu_count() : t; }
+
 }  // namespace skl
+
+extern "C" int skltlt_tune_skr2k_small_tiles(int tiles)
+{
+    skl::skr2k_set_small_tiles(tiles);
+    return SKLTLT_OK;
+}

@@ -169,3 +169,28 @@ def test_deterministic():
     r1 = run_factor(A, block_size=64)
     r2 = run_factor(A, block_size=64)
     assert np.array_equal(r1["A"], r2["A"]) and np.array_equal(r1["ipiv"], r2["ipiv"])
+
+
+@pytest.mark.parametrize("precision", [binding.FP64, binding.FP32_UPDATE])
+def test_trailing_update_tilings_bit_identical(precision):
+    """The 128x128-tile and the 64x64-tile trailing updates sum every element
+    in the same K order: forcing either tiling for every update of an
+    n = 2600 factorization (ragged against both tile sizes, trailing blocks
+    from 2599 down to a few rows) gives the same bytes, and the FP64 result
+    matches the oracle."""
+    L = binding.lib()
+    n = 2600
+    A = inputs.skew_normal(n, 77)
+    note(f"[tilings] n={n} precision={precision}")
+    try:
+        assert L.skltlt_tune_skr2k_small_tiles(0) == 0            # 128-tiles only
+        r_big = run_factor(A, block_size=128, precision=precision)
+        assert L.skltlt_tune_skr2k_small_tiles(1 << 30) == 0      # 64-tiles only
+        r_small = run_factor(A, block_size=128, precision=precision)
+    finally:
+        L.skltlt_tune_skr2k_small_tiles(-1)
+    assert np.array_equal(r_big["ipiv"], r_small["ipiv"])
+    assert np.array_equal(r_big["t"], r_small["t"])
+    assert np.array_equal(r_big["A"], r_small["A"])
+    if precision == binding.FP64:
+        check_against_oracle(A, r_small)
