@@ -24,6 +24,7 @@
 #include "wave_max.h"
 
 #include <climits>
+#include <type_traits>
 #include <cmath>
 #include <mutex>
 
@@ -308,7 +309,44 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
         // every column's operands for each of its products.  Each wave takes
         // every fourth block, kGrp at a time, their C loads issued before the
         // products.
-        if (cp < n - 1) {
+        // The matrix accesses of the update go through a bounds-checked
+        // buffer resource over the matrix (when it spans less than 2 GB):
+        // a lane without an entry passes the end of the buffer as its
+        // offset, so its load returns 0 and its store is dropped, and every
+        // lane issues the same loads and stores.  With the accesses in
+        // branches the compiler waited for each store to complete before the
+        // next (its waits must hold on every path).
+        const size_t span64 = ((size_t)(n - 1) * lda + n) * sizeof(double);
+        const int span = __builtin_amdgcn_readfirstlane(
+            (int)(span64 < (size_t)0x7fffffff ? span64 : (size_t)0));
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        auto update = [&](auto fast) {
+            constexpr bool kFast = decltype(fast)::value;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(double *)A, (short)0, kFast ? span : 0, 0x00020000);
+            auto ld_c = [&](bool on, int gj, int gi) -> double {
+                if constexpr (kFast) {
+                    const u32x2 d = __builtin_amdgcn_raw_buffer_load_b64(
+                        rs, on ? (gj * lda + gi) * (int)sizeof(double) : span, 0, 0);
+                    return __longlong_as_double(
+                        (long long)(((unsigned long long)d.y << 32) | d.x));
+                } else {
+                    return on ? A[(size_t)gj * lda + gi] : 0.0;
+                }
+            };
+            auto st_c = [&](bool on, int gj, int gi, double v) {
+                if constexpr (kFast) {
+                    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+                    u32x2 d;
+                    d.x = (unsigned)bits;
+                    d.y = (unsigned)(bits >> 32);
+                    __builtin_amdgcn_raw_buffer_store_b64(
+                        d, rs, on ? (gj * lda + gi) * (int)sizeof(double) : span, 0, 0);
+                } else {
+                    if (on)
+                        A[(size_t)gj * lda + gi] = v;
+                }
+            };
             constexpr int kGrp = 2; // (4 spilled two VGPRs at four workgroups per CU)
             const int m = n - cp;
             const int nt = (m + 15) / 16;
@@ -330,8 +368,7 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int gj = j0[u] + lk + 4 * q;
-                        cv[u][q] = (ok[u] && gi[u] < n && gj < gi[u])
-                                       ? A[(size_t)gj * lda + gi[u]] : 0.0;
+                        cv[u][q] = ld_c(ok[u] && gi[u] < n && gj < gi[u], gj, gi[u]);
                     }
                 }
 #pragma unroll
@@ -354,11 +391,16 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int gj = j0[u] + lk + 4 * q;
-                        if (ok[u] && gi[u] < n && gj < gi[u])
-                            A[(size_t)gj * lda + gi[u]] = cv[u][q] - acc[q];
+                        st_c(ok[u] && gi[u] < n && gj < gi[u], gj, gi[u], cv[u][q] - acc[q]);
                     }
                 }
             }
+        };
+        if (cp < n - 1) {
+            if (span > 0)
+                update(std::integral_constant<bool, true>());
+            else
+                update(std::integral_constant<bool, false>());
         }
         // carry the last column of L into the next panel
         if (valid && i >= cp + 1)
