@@ -215,7 +215,9 @@ int skltlt_batched_workspace_size(int batch, size_t *bytes);
  *   log_abs_pf, sign (device) arrays of batch entries, or both NULL to skip
  *                the Pfaffians.
  *   info (device) batch ints or NULL: 0 = done, -1 = entry rejected
- *                (n[i] < 0, n[i] > max_n or lda[i] < max(1, n[i])); a
+ *                (n[i] < 0, n[i] > max_n, lda[i] < max(1, n[i]), or a
+ *                matrix spanning 2 GiB or more: (n[i]-1) lda[i] + n[i]
+ *                doubles >= 2^31 - 1 bytes); a
  *                rejected entry's matrix, t and ipiv are not touched, and
  *                its log_abs_pf / sign (when given) are set to NaN / 0.
  *   max_n (host) upper bound of the n[i], at most skltlt_batched_max_n().

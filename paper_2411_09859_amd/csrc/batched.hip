@@ -24,7 +24,6 @@
 #include "wave_max.h"
 
 #include <climits>
-#include <type_traits>
 #include <cmath>
 #include <mutex>
 
@@ -95,6 +94,34 @@ struct BatchShared {
 typedef __attribute__((address_space(1))) double gdouble;
 typedef __attribute__((address_space(1))) int gint;
 
+// Matrix accesses of the column steps and the trailing update go through a
+// bounds-checked buffer resource over the matrix (the entry point rejects a
+// member that spans 2 GiB or more): a lane with nothing to access passes the
+// end of the buffer as its offset, so its load returns 0 and its store is
+// dropped, and every lane issues the same loads and stores.  With the
+// accesses in branches the compiler's waits (which must hold on every path)
+// waited for each store to complete before the next access.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double ld_m(__amdgpu_buffer_rsrc_t rs, int off)
+{
+    const u32x2 d = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+    return __longlong_as_double((long long)(((unsigned long long)d.y << 32) | d.x));
+}
+__device__ __forceinline__ void st_m(__amdgpu_buffer_rsrc_t rs, int off, double v)
+{
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    u32x2 d;
+    d.x = (unsigned)bits;
+    d.y = (unsigned)(bits >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(d, rs, off, 0, 0);
+}
+// bytes a member spans, and whether the buffer accesses can reach all of it
+__device__ __host__ inline size_t member_span(int n, int lda)
+{
+    return ((size_t)(n > 1 ? n - 1 : 0) * (size_t)lda + (size_t)n) * sizeof(double);
+}
+constexpr size_t kMaxMemberSpan = 0x7fffffff;
+
 __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, int n,
                            gdouble *__restrict__ t, gint *__restrict__ ipiv, int bs)
 {
@@ -105,6 +132,13 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
         ipiv[0] = 0;
     if (n < 2)
         return;
+    const int span = __builtin_amdgcn_readfirstlane((int)member_span(n, lda));
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(double *)A, (short)0, span, 0x00020000);
+    // (unsigned arithmetic: lanes past n form offsets they never use)
+    auto moff = [&](int col, int row) {
+        return (int)(((unsigned)col * (unsigned)lda + (unsigned)row) * (unsigned)sizeof(double));
+    };
 
     for (int k0 = 0; k0 < n - 1; k0 += bs) {
         const int nb = min(bs, n - 1 - k0);
@@ -122,6 +156,9 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
         for (int a = tid; a < kBLd; a += kBT)
             sh.hv[a] = 0.0;
         double ycol = valid ? A[(size_t)k0 * lda + i] : 0.0;
+        // nothing in flight when the steps begin (a load pending from here
+        // makes the compiler wait for every access at each step's start)
+        wait_vm();
         __syncthreads();
 
         for (int j = 0; j < nb; ++j) {
@@ -219,12 +256,13 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
             // on: loads in alternative branches into one register made the
             // second wait for the first)
             const bool xrow = valid && i > r;
-            double av = 0.0, bv = 0.0;
-            if (xrow) {
-                av = A[(size_t)r * lda + i];
-                if (p != r && i != p)
-                    bv = A[(i > p) ? (size_t)p * lda + i : (size_t)i * lda + p];
-            }
+            // entry (i, r), and the entry this row exchanges with (i, p) or
+            // (p, i) of the lower triangle
+            const bool xch = xrow && p != r && i != p;
+            const int off_r = moff(r, i);
+            const int off_x = (i > p) ? moff(p, i) : moff(i, p);
+            const double av = ld_m(rs, xrow ? off_r : span);
+            const double bv = ld_m(rs, xch ? off_x : span);
             // row r hands its x to row p
             if (i == r)
                 sh.bc_xr = x;
@@ -238,29 +276,17 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
             if (i == p && p != r)
                 x = sh.bc_xr;
             // symmetric exchange r <-> p of the trailing matrix (lower
-            // storage), then ycol = Y'[i, r]
-            if (xrow) {
-                gdouble *colr = A + (size_t)r * lda;
-                double ynew;
-                if (p == r) {
-                    ynew = av;
-                } else if (i > p) {
-                    A[(size_t)p * lda + i] = av;
-                    if (last)
-                        colr[i] = bv;
-                    ynew = bv;
-                } else if (i < p) {
-                    A[(size_t)i * lda + p] = -av;
-                    if (last)
-                        colr[i] = -bv;
-                    ynew = -bv;
-                } else {
-                    if (last)
-                        colr[p] = -av;
-                    ynew = -av;
-                }
+            // storage), then ycol = Y'[i, r]: entry (i, r) moves to (p, i)
+            // (i > p) or, negated, to (i, p) (i < p); the new (i, r) is the
+            // old (p, i) (i > p), minus the old (i, p) (i < p), or minus the
+            // old (p, r) at i = p, and is written back only at the panel's
+            // last column (later columns read it from ycol).  ycol is set
+            // before the stores are issued.
+            const double ynew = (p == r) ? av : ((i > p) ? bv : ((i < p) ? -bv : -av));
+            if (xrow)
                 ycol = ynew;
-            }
+            st_m(rs, xch ? off_x : span, (i > p) ? av : -av);
+            st_m(rs, (xrow && p != r && last) ? off_r : span, ynew);
             // new column of L
             if (valid && i > r)
                 sh.Lp[i][j + 1] = (tau != 0.0) ? x / tau : 0.0;
@@ -309,44 +335,8 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
         // every column's operands for each of its products.  Each wave takes
         // every fourth block, kGrp at a time, their C loads issued before the
         // products.
-        // The matrix accesses of the update go through a bounds-checked
-        // buffer resource over the matrix (when it spans less than 2 GB):
-        // a lane without an entry passes the end of the buffer as its
-        // offset, so its load returns 0 and its store is dropped, and every
-        // lane issues the same loads and stores.  With the accesses in
-        // branches the compiler waited for each store to complete before the
-        // next (its waits must hold on every path).
-        const size_t span64 = ((size_t)(n - 1) * lda + n) * sizeof(double);
-        const int span = __builtin_amdgcn_readfirstlane(
-            (int)(span64 < (size_t)0x7fffffff ? span64 : (size_t)0));
-        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        auto update = [&](auto fast) {
-            constexpr bool kFast = decltype(fast)::value;
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void *)(double *)A, (short)0, kFast ? span : 0, 0x00020000);
-            auto ld_c = [&](bool on, int gj, int gi) -> double {
-                if constexpr (kFast) {
-                    const u32x2 d = __builtin_amdgcn_raw_buffer_load_b64(
-                        rs, on ? (gj * lda + gi) * (int)sizeof(double) : span, 0, 0);
-                    return __longlong_as_double(
-                        (long long)(((unsigned long long)d.y << 32) | d.x));
-                } else {
-                    return on ? A[(size_t)gj * lda + gi] : 0.0;
-                }
-            };
-            auto st_c = [&](bool on, int gj, int gi, double v) {
-                if constexpr (kFast) {
-                    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-                    u32x2 d;
-                    d.x = (unsigned)bits;
-                    d.y = (unsigned)(bits >> 32);
-                    __builtin_amdgcn_raw_buffer_store_b64(
-                        d, rs, on ? (gj * lda + gi) * (int)sizeof(double) : span, 0, 0);
-                } else {
-                    if (on)
-                        A[(size_t)gj * lda + gi] = v;
-                }
-            };
+        // C -= ... (loads and stores through the buffer resource)
+        if (cp < n - 1) {
             constexpr int kGrp = 2; // (4 spilled two VGPRs at four workgroups per CU)
             const int m = n - cp;
             const int nt = (m + 15) / 16;
@@ -368,7 +358,8 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int gj = j0[u] + lk + 4 * q;
-                        cv[u][q] = ld_c(ok[u] && gi[u] < n && gj < gi[u], gj, gi[u]);
+                        cv[u][q] = ld_m(rs, (ok[u] && gi[u] < n && gj < gi[u]) ? moff(gj, gi[u])
+                                                                               : span);
                     }
                 }
 #pragma unroll
@@ -391,16 +382,11 @@ __device__ void factor_one(BatchShared &sh, gdouble *__restrict__ A, int lda, in
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int gj = j0[u] + lk + 4 * q;
-                        st_c(ok[u] && gi[u] < n && gj < gi[u], gj, gi[u], cv[u][q] - acc[q]);
+                        st_m(rs, (ok[u] && gi[u] < n && gj < gi[u]) ? moff(gj, gi[u]) : span,
+                             cv[u][q] - acc[q]);
                     }
                 }
             }
-        };
-        if (cp < n - 1) {
-            if (span > 0)
-                update(std::integral_constant<bool, true>());
-            else
-                update(std::integral_constant<bool, false>());
         }
         // carry the last column of L into the next panel
         if (valid && i >= cp + 1)
@@ -573,7 +559,8 @@ __global__ __launch_bounds__(kBT, kBPerCu) void batched_kernel(int batch, const 
             break;
         const int n = nv[idx];
         const int lda = ldav[idx];
-        const bool ok = (n >= 0) && (n <= max_n) && (n <= kBT) && (lda >= (n > 1 ? n : 1));
+        const bool ok = (n >= 0) && (n <= max_n) && (n <= kBT) && (lda >= (n > 1 ? n : 1)) &&
+                        member_span(n, lda) < kMaxMemberSpan;
         if (info && tid == 0)
             info[idx] = ok ? 0 : -1;
         if (!ok) {

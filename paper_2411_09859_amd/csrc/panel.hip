@@ -114,8 +114,6 @@ __device__ __forceinline__ void st_xcd(double *p, double v, bool local)
     else
         st_dev(p, v);
 }
-// Wait until this wave's outstanding memory operations have completed.
-__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Stores into the row-major mirror of L through a bounds-checked buffer
 // resource.  Every thread issues both forms of the store of a step, plain

@@ -1,11 +1,16 @@
-// Wave-level helpers shared by the panel and batched kernels: reading a
-// double from one lane, the largest key over a wave with DPP moves (no
-// LDS), and FP64 FMAs whose second factor is broadcast inside 16-lane rows.
+// Wave-level helpers shared by the panel and batched kernels: waiting for
+// the wave's memory operations, reading a double from one lane, the largest
+// key over a wave with DPP moves (no LDS), and FP64 FMAs whose second factor
+// is broadcast inside 16-lane rows.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace skl {
+
+// Wait until this wave's outstanding memory operations have completed
+// (s_waitcnt vmcnt(0)).
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 __device__ __forceinline__ double readlane_f64(double v, int l)
 {

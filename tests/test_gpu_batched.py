@@ -85,6 +85,45 @@ def test_batched_rejects_invalid_members():
     check_against_oracle(good, res[0], check_pf=True)
 
 
+def test_batched_rejects_member_spanning_2gib():
+    """A member whose matrix spans 2 GiB or more ((n-1) lda + n doubles) is
+    rejected like the other invalid members; the buffer given for it is
+    allocated in full (3.4 GB), so no address the kernel could form lies
+    outside it.  The other member of the batch is factored as usual."""
+    import torch
+    note("[batched] member spanning 2 GiB")
+    n, lda = 200, 1 << 21
+    assert ((n - 1) * lda + n) * 8 >= 2 ** 31 - 1
+    big = torch.zeros((n, lda), dtype=torch.float64, device="cuda")  # column-major lda x n
+    M = inputs.skew_normal(n, 3)
+    big[:, :n] = torch.from_numpy(np.ascontiguousarray(M.T)).to("cuda")
+    good = inputs.skew_normal(40, 4)
+    gbuf = torch.from_numpy(np.asfortranarray(good)).to("cuda")  # stride (1, 40)
+    ts = [torch.full((n - 1,), -5.0, dtype=torch.float64, device="cuda") for n in (40, n)]
+    ps = [torch.full((n,), -1, dtype=torch.int32, device="cuda") for n in (40, n)]
+    dev = "cuda"
+    n_dev = torch.tensor([40, n], dtype=torch.int32, device=dev)
+    lda_dev = torch.tensor([40, lda], dtype=torch.int32, device=dev)
+    A_ptrs = torch.tensor([gbuf.data_ptr(), big.data_ptr()], dtype=torch.int64, device=dev)
+    t_ptrs = torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64, device=dev)
+    p_ptrs = torch.tensor([p.data_ptr() for p in ps], dtype=torch.int64, device=dev)
+    la = torch.zeros(2, dtype=torch.float64, device=dev)
+    sg = torch.full((2,), 9, dtype=torch.int32, device=dev)
+    info = torch.full((2,), 5, dtype=torch.int32, device=dev)
+    work = binding.alloc_workspace(binding.batched_workspace_size(2))
+    binding.batched(n_dev, A_ptrs, lda_dev, t_ptrs, p_ptrs, la, sg, info, 256, 0, binding.FP64, work)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, -1]
+    assert np.isnan(float(la[1])) and int(sg[1]) == 0
+    assert np.all(ts[1].cpu().numpy() == -5.0) and np.all(ps[1].cpu().numpy() == -1)
+    assert np.array_equal(big[:, :n].cpu().numpy().T, M)
+    del big
+    res = {"A": np.asfortranarray(gbuf.cpu().numpy()), "t": ts[0].cpu().numpy(),
+           "ipiv": ps[0].cpu().numpy(), "log_abs_pf": float(la[0]), "sign": int(sg[0]),
+           "info": 0}
+    check_against_oracle(good, res, check_pf=True)
+
+
 def test_batched_argument_errors():
     import torch
     n = torch.zeros(1, dtype=torch.int32, device="cuda")
