@@ -672,7 +672,9 @@ def main():
         traffic, traffic_src = measured_traffic(n, b)
         busy, busy_src = measured_mfma_busy(n, b)
         roofs["skr2k"] = {
-            "kernel": "skr2k_kernel<double>", "bound": "mfma", "achieved": achieved,
+            "kernel": "skr2k_kernel<double> (128x128 tiles) and skr2k_small_kernel<double> "
+                      "(64x64 tiles, trailing blocks with fewer 128-tiles than CUs)",
+            "bound": "mfma", "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
             "traffic": traffic, "traffic_source": traffic_src,
             "traffic_over_algorithmic": (traffic / alg) if traffic else None,
