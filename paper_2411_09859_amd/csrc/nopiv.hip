@@ -117,7 +117,8 @@ struct NpRow {
                 bcast_fma<0, 16, 64, kNpNS>(acc, Lreg, hb[4 % kNB]);
         bcast_fma<0, kRing, 0, kRing>(acc, Lnew, hr);
         double s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-        s += __shfl_xor(s, 64 / kNpTPR, 64); // the row's other thread
+        static_assert(64 / kNpTPR == 32, "the row's two threads are 32 lanes apart");
+        s = xor_add<32>(s); // the row's other thread (lane swap, no LDS)
         return s;
     }
     // after the last insert: every column in Lreg

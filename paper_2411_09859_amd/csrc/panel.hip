@@ -399,33 +399,6 @@ __device__ __forceinline__ void find_pivot(PivotLds<NT / 64> &pl, const SlotIO &
 }
 
 
-__device__ __forceinline__ double dbl_of(unsigned lo, unsigned hi)
-{
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// One step of an xor butterfly over the lanes OFF = 32 or 16 apart: every
-// lane gets s + s(lane ^ OFF), with the gfx950 lane-swap instructions (VALU,
-// no LDS).  Swapping a register with itself leaves, in the two outputs, the
-// lane's own half and the partner half, so their sum is the butterfly step
-// (the same sum as s + shfl_xor(s, OFF): addition commutes).
-template <int OFF>
-__device__ __forceinline__ double xor_add(double s)
-{
-    static_assert(OFF == 32 || OFF == 16, "swap distance");
-    const unsigned long long b = (unsigned long long)__double_as_longlong(s);
-    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
-    if constexpr (OFF == 32) {
-        const auto l2 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-        const auto h2 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-        return dbl_of(l2[0], h2[0]) + dbl_of(l2[1], h2[1]);
-    } else {
-        const auto l2 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-        const auto h2 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-        return dbl_of(l2[0], h2[0]) + dbl_of(l2[1], h2[1]);
-    }
-}
-
 // Whether every working group of this launch runs on one XCD: each group
 // publishes its XCC_ID (hardware register) tagged with the panel's first
 // column and reads all the others' (device scope).  Every group reaches the
@@ -1063,11 +1036,8 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
                 dob = me0 * hoa;
             }
         }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            dk += __shfl_xor(dk, off, 64);
-            dob += __shfl_xor(dob, off, 64);
-        }
+        dk = wave_sum_f64(dk);
+        dob = wave_sum_f64(dob);
         if (lane == 0) {
             dred[0][wave] = dk;
             dred[1][wave] = dob;

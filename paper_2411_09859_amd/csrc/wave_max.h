@@ -1,7 +1,8 @@
-// Wave-level helpers shared by the panel and batched kernels: waiting for
-// the wave's memory operations, reading a double from one lane, the largest
-// key over a wave with DPP moves (no LDS), and FP64 FMAs whose second factor
-// is broadcast inside 16-lane rows.
+// Wave-level helpers shared by the panel, unpivoted and batched kernels:
+// waiting for the wave's memory operations, sums across lanes by lane swaps
+// and DPP moves, reading a double from one lane, the largest key over a wave
+// with DPP moves (no LDS), and FP64 FMAs whose second factor is broadcast
+// inside 16-lane rows.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,6 +12,60 @@ namespace skl {
 // Wait until this wave's outstanding memory operations have completed
 // (s_waitcnt vmcnt(0)).
 __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+__device__ __forceinline__ double dbl_of(unsigned lo, unsigned hi)
+{
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// One step of an xor butterfly over the lanes OFF = 32 or 16 apart: every
+// lane gets s + s(lane ^ OFF), with the gfx950 lane-swap instructions (VALU,
+// no LDS).  Swapping a register with itself leaves, in the two outputs, the
+// lane's own half and the partner half, so their sum is the butterfly step
+// (the same sum as s + shfl_xor(s, OFF): addition commutes).
+template <int OFF>
+__device__ __forceinline__ double xor_add(double s)
+{
+    static_assert(OFF == 32 || OFF == 16, "swap distance");
+    const unsigned long long b = (unsigned long long)__double_as_longlong(s);
+    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+    if constexpr (OFF == 32) {
+        const auto l2 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h2 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        return dbl_of(l2[0], h2[0]) + dbl_of(l2[1], h2[1]);
+    } else {
+        const auto l2 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h2 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        return dbl_of(l2[0], h2[0]) + dbl_of(l2[1], h2[1]);
+    }
+}
+
+// one DPP move of a double (both dwords through the same pattern CTRL)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return dbl_of((unsigned)lo, (unsigned)hi);
+}
+
+// Sum of s over the 64 lanes of a wave, the same bits in every lane: inside
+// each 16-lane row lanes are paired by DPP moves (xor 1 and xor 2 by quad
+// permutations, then the half-row and row mirrors, which pair lanes whose
+// partial sums are by then equal within their quad and half-row), then the
+// rows by the lane swaps 16 and 32 apart.  At every step a lane adds its
+// own partial sum and its partner's, which the partner adds the other way
+// round: addition commutes, so all lanes keep equal bits.  All VALU, no LDS.
+__device__ __forceinline__ double wave_sum_f64(double s)
+{
+    s = s + dpp_f64<0xB1>(s);  // quad_perm [1,0,3,2]
+    s = s + dpp_f64<0x4E>(s);  // quad_perm [2,3,0,1]
+    s = s + dpp_f64<0x141>(s); // row_half_mirror
+    s = s + dpp_f64<0x140>(s); // row_mirror
+    s = xor_add<16>(s);
+    return xor_add<32>(s);
+}
 
 __device__ __forceinline__ double readlane_f64(double v, int l)
 {
