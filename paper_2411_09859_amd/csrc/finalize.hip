@@ -150,6 +150,34 @@ __global__ __launch_bounds__(1024) void gather_reg_kernel(double *__restrict__ A
     }
 }
 
+// One 1024-thread workgroup per column, the column staged in LDS: read
+// once in order (coalesced), then every entry written in order from its
+// permuted source in LDS.  The register form above reads its sources at
+// permuted addresses, one 8-byte entry per memory granule when the
+// permutation scatters (it does, after thousands of pivots).
+constexpr int kGatherLdsMax = 20480; // doubles: 160 KB of LDS
+__global__ __launch_bounds__(1024) void gather_lds_kernel(double *__restrict__ A, int lda, int n,
+                                                          int b, int nblk,
+                                                          const int *__restrict__ gmap)
+{
+    extern __shared__ double col[];
+    const int a = blockIdx.x;
+    const GatherCol gc = gather_col(a, n, b, nblk);
+    if (gc.len <= 0)
+        return;
+    double *cp = A + (size_t)a * lda + gc.lo;
+    const int *g = gmap + (size_t)gc.B * n + gc.lo;
+    for (int q = threadIdx.x; q < gc.len; q += blockDim.x)
+        col[q] = cp[q];
+    __syncthreads();
+    for (int q = threadIdx.x; q < gc.len; q += blockDim.x) {
+        int src = g[q] - gc.lo;
+        if (src < 0 || src >= gc.len)
+            src = q; // cannot happen for valid pivots; keeps the read in range
+        __builtin_nontemporal_store(col[src], &cp[q]);
+    }
+}
+
 // Columns longer than the register version holds: gather into a scratch
 // column of the (no longer needed) work matrix, then copy back.
 __global__ __launch_bounds__(1024) void gather_scratch_kernel(double *__restrict__ A, int lda,
@@ -176,7 +204,12 @@ __global__ __launch_bounds__(1024) void gather_scratch_kernel(double *__restrict
         cp[q] = tmp[q];
 }
 
-void finalize_init_attrs() {}
+void finalize_init_attrs()
+{
+    (void)hipFuncSetAttribute((const void *)gather_lds_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kGatherLdsMax * (int)sizeof(double));
+}
 
 hipError_t launch_finalize(double *A, int lda, int n, int b, const int *ipiv,
                            const FactorWs &ws, hipStream_t s)
@@ -199,7 +232,10 @@ hipError_t launch_finalize(double *A, int lda, int n, int b, const int *ipiv,
         return hipSuccess;
     const dim3 grid(n - 2 > 0 ? n - 2 : 1), blk(1024);
     const int *gm = ws.gmap;
-    if (maxlen <= 4 * 1024)
+    if (maxlen > 4 * 1024 && maxlen <= kGatherLdsMax)
+        hipLaunchKernelGGL(gather_lds_kernel, grid, blk, (size_t)maxlen * sizeof(double), s, A,
+                           lda, n, b, nblk, gm);
+    else if (maxlen <= 4 * 1024)
         hipLaunchKernelGGL(gather_reg_kernel<4>, grid, blk, 0, s, A, lda, n, b, nblk, gm);
     else if (maxlen <= 8 * 1024)
         hipLaunchKernelGGL(gather_reg_kernel<8>, grid, blk, 0, s, A, lda, n, b, nblk, gm);
