@@ -1,13 +1,21 @@
 """Autotuner for the batched kernel: panel width per matrix order and
 persistent workgroups per CU.
 
-For each size class it times skltlt_batched on a seeded batch of that class
-for every candidate pair (panel width, workgroups per CU) (HIP events, median
-of a few repetitions) and keeps the fastest.  The width applies to the
-matrices of that class; the workgroups per CU to batches whose largest order
-falls in the class.  The result is written twice: ``tune_batched.json`` (the
-measurements) and ``csrc/batched_table.h`` (the compiled-in lookup used when
-block_size = 0).  Rebuild the library after tuning.
+Two measurements per size class (HIP events, median of a few repetitions):
+1. the panel width: a seeded batch of matrices of that class only, timed for
+   every candidate pair (panel width, workgroups per CU); the width of the
+   fastest pair applies to the matrices of that class;
+2. the workgroups per CU: they apply to a whole batch, chosen by the batch's
+   largest order (the host knows no more of a batch than its bound), so they
+   are timed on a mixed batch whose orders spread evenly from 16 up to the
+   class's upper end, each matrix at the compiled table's width.
+(On a batch of [226, 256] alone three workgroups per CU beat four by 3 %;
+on a batch spread over [16, 256], which a largest order of 256 also
+describes, four beat three by 6 %.)
+The result is written twice: ``tune_batched.json`` (the measurements) and
+``csrc/batched_table.h`` (the compiled-in lookup used when block_size = 0).
+Rebuild the library after tuning; if the widths changed, tune again so that
+the second measurement sees them.
 
     python -m paper_2411_09859_amd.tune_batched [--count 4096]
 """
@@ -50,10 +58,10 @@ def tune(count=4096, seed=7, verbose=True):
     meas = {}
     try:
         for lo, hi in CLASSES:
+            # 1. panel width on a batch of this class only
             sizes, sing = inputs.batch_sizes(count, seed + lo, lo=lo, hi=hi,
                                              singular_fraction=0.0)
-            mats = inputs.batch_matrices(sizes, sing, seed + lo)
-            arena = Arena(mats)
+            arena = Arena(inputs.batch_matrices(sizes, sing, seed + lo))
             res = {}
             for g in WGPC:
                 if L.skltlt_tune_batched_wgpc(g) != 0:
@@ -61,12 +69,26 @@ def tune(count=4096, seed=7, verbose=True):
                 for bs in WIDTHS:
                     res[f"{bs}x{g}"] = time_arena(torch, arena, bs)
             best = min(res, key=res.get)
-            bs, g = (int(x) for x in best.split("x"))
-            meas[f"{lo}-{hi}"] = {"ms": res, "best": {"width": bs, "wgpc": g}, "count": count}
+            bs = int(best.split("x")[0])
+            del arena
+            # 2. workgroups per CU on a batch spread over [16, hi]
+            sizes, sing = inputs.batch_sizes(count, seed + 1000 + hi, lo=16, hi=hi,
+                                             singular_fraction=0.0)
+            arena = Arena(inputs.batch_matrices(sizes, sing, seed + 1000 + hi))
+            mixed = {}
+            for g in WGPC:
+                L.skltlt_tune_batched_wgpc(g)
+                mixed[str(g)] = time_arena(torch, arena, 0)
+            del arena
+            g = int(min(mixed, key=mixed.get))
+            meas[f"{lo}-{hi}"] = {"ms": res, "best_width": bs,
+                                  "mixed_16_to_hi_ms_by_wgpc": mixed, "best_wgpc": g,
+                                  "count": count}
             table.append((hi, bs, g))
             if verbose:
-                print(f"[tune] n in [{lo},{hi}]: best width {bs} x {g} per CU "
-                      f"{res[best]:.3f} ms; width 16 x 4: {res['16x4']:.3f} ms", flush=True)
+                print(f"[tune] n in [{lo},{hi}]: width {bs} ({res[best]:.3f} ms alone); "
+                      f"batch over [16,{hi}]: {g} per CU {mixed[str(g)]:.3f} ms "
+                      f"(4 per CU {mixed['4']:.3f} ms)", flush=True)
     finally:
         L.skltlt_tune_batched_wgpc(0)
     return table, meas

@@ -127,3 +127,40 @@ def test_noalloc_batched_limits():
                                     16, 0, 1, None) == binding.SKLTLT_ENOTSUP
     assert L.skltlt_batched_noalloc(0, None, None, None, None, None, None, None, None,
                                     16, 0, 0, None) == binding.SKLTLT_OK
+
+
+def test_tuner_tables_match_their_measurements(tmp_path):
+    """The compiled-in tables are what the tuners write from the committed
+    measurements: regenerating the headers from the JSON files gives the
+    headers in csrc/ byte for byte, and the library's default widths follow
+    the single-matrix table."""
+    import json
+    import math
+
+    from paper_2411_09859_amd import tune_batched, tune_factor
+    _lib_or_skip()
+    pkg = os.path.dirname(binding.LIB_PATH)
+    fm = json.load(open(os.path.join(pkg, "tune_factor.json")))["orders"]
+    ftable = [(int(n), int(v["best"])) for n, v in sorted(fm.items(), key=lambda kv: int(kv[0]))]
+    for n, v in fm.items():  # the best is the fastest measured width
+        assert int(v["best"]) == int(min(v["ms"], key=v["ms"].get))
+    tune_factor.write_outputs(ftable, fm, out_dir=str(tmp_path))
+    assert (tmp_path / "factor_table.h").read_text() == \
+        open(os.path.join(pkg, "csrc", "factor_table.h")).read()
+    bm = json.load(open(os.path.join(pkg, "tune_batched.json")))["classes"]
+    btable = []
+    for cls, v in sorted(bm.items(), key=lambda kv: int(kv[0].split("-")[1])):
+        hi = int(cls.split("-")[1])
+        assert v["best_width"] == int(min(v["ms"], key=v["ms"].get).split("x")[0])
+        mixed = v["mixed_16_to_hi_ms_by_wgpc"]
+        assert v["best_wgpc"] == int(min(mixed, key=mixed.get))
+        btable.append((hi, v["best_width"], v["best_wgpc"]))
+    tune_batched.write_outputs(btable, bm, out_dir=str(tmp_path))
+    assert (tmp_path / "batched_table.h").read_text() == \
+        open(os.path.join(pkg, "csrc", "batched_table.h")).read()
+    L = binding.lib()
+    for k, (n, b) in enumerate(ftable):
+        assert L.skltlt_default_block_size(n) == b
+        if k + 1 < len(ftable):  # just below the next class boundary
+            edge = int(math.sqrt(n * ftable[k + 1][0]))
+            assert L.skltlt_default_block_size(edge) == b
