@@ -57,8 +57,8 @@ def kernel_times(lib):
 def skr2k_bytes(n, b, per_elem=16.0):
     """HBM bytes of all skr2k launches of one factorization: each launch reads
     the strict lower triangle of the trailing block once and writes it
-    (per_elem = 16 B per element: the algorithmic minimum; 24 B with the
-    negated mirror store the full-storage design adds) and reads the two
+    (per_elem = 16 B per element, the algorithmic minimum, which the
+    lower-triangle storage of the work matrices also moves) and reads the two
     m x K operand panels once."""
     tot = 0.0
     k0 = 0
@@ -668,7 +668,6 @@ def main():
         flops_per_launch = sk["flops"] / sk["launches"]
         achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
         alg = skr2k_bytes(n, b, 16.0) * steps / sk["launches"]
-        design = skr2k_bytes(n, b, 24.0) * steps / sk["launches"]
         traffic, traffic_src = measured_traffic(n, b)
         busy, busy_src = measured_mfma_busy(n, b)
         roofs["skr2k"] = {
@@ -681,7 +680,6 @@ def main():
             "mfma_busy": busy, "mfma_busy_source": busy_src,
             "flops_per_launch": flops_per_launch, "launches": sk["launches"] // steps,
             "algorithmic_bytes_per_launch": alg,
-            "design_bytes_per_launch": design,
             "avg_launch_ms": per_launch_ms,
             "hbm_gbs_algorithmic": alg / (per_launch_ms * 1e-3) / 1e9,
             "hbm_frac_algorithmic": alg / (per_launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}

@@ -26,7 +26,7 @@ struct Slot {
 
 // Device workspace of skltlt_factor, carved from the caller's buffer.
 struct FactorWs {
-    double *W[2];      // full skew copies of the trailing matrix (ping-pong), ld = ldw
+    double *W[2];      // the trailing matrix's lower triangle (ping-pong), ld = ldw
     int ldw;
     int *perm;         // panel permutation: perm[pos] = row at the panel start
     double *mirror;    // physical panel rows, row-major, ld = ldm
@@ -65,7 +65,7 @@ struct PanelShape {
     size_t lds;
 };
 PanelShape panel_shape(int n, int k0, int b, int max_groups);
-// W: the full skew trailing matrix as of the panel start (read only).
+// W: the trailing matrix as of the panel start, its lower triangle (read only).
 hipError_t launch_panel(double *A, int lda, const double *W, int n, int k0, int nb, int b,
                         double *t, int *ipiv, const FactorWs &ws, int want32,
                         const PanelShape &sh, hipStream_t s);
@@ -92,14 +92,24 @@ void skr2k_set_small_tiles(int t);
 hipError_t launch_skr2k(const double *Wc, double *Wn, int n, int cp, int nq,
                         const FactorWs &ws, int precision, hipStream_t s);
 
-// W = the full skew matrix whose strict lower triangle is A's.
-hipError_t launch_init_full(const double *A, int lda, int n, double *W, int ldw, hipStream_t s);
+// Lower triangle of W = A's strict lower triangle, zero diagonal.
+hipError_t launch_init_lower(const double *A, int lda, int n, double *W, int ldw, hipStream_t s);
 
 hipError_t launch_finalize(double *A, int lda, int n, int b, const int *ipiv,
                            const FactorWs &ws, hipStream_t s);
 
 hipError_t launch_pfaffian(int n, const double *t, const int *ipiv,
                            double *log_abs_pf, int *sign, hipStream_t s);
+
+// Entry (row, col) of a skew-symmetric matrix kept as its lower triangle
+// (column-major, leading dimension ld): the offset of the stored entry, and
+// in neg whether the entry is its negation (an upper entry, row < col).  The
+// diagonal maps to the stored diagonal.
+__device__ __forceinline__ size_t skew_at(int row, int col, int ld, bool &neg)
+{
+    neg = row < col;
+    return neg ? (size_t)row * ld + col : (size_t)col * ld + row;
+}
 
 // Lower-triangle tile enumeration: tau = I (I + 1) / 2 + J with 0 <= J <= I.
 __device__ __forceinline__ void tile_of(int tau, int *ti, int *tj)

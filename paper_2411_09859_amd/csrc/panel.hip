@@ -32,11 +32,12 @@
 // The exchanges are never applied to memory here.  A register row always
 // holds the same row of the panel-start matrix Y0 (its "original" row) and
 // only the label it stands for changes: the one that held r continues as p
-// with its x, the one that held p becomes row r, final for this panel.  The
-// trailing matrix is kept in full skew storage (both triangles), so entry
-// (label i, label r) of the exchanged matrix is Y0[orig(i), orig(r)], one
-// coalesced column of Y0 per step.  The skr2k kernel applies the panel's
-// permutation when it forms the next trailing matrix.  The panel writes
+// with its x, the one that held p becomes row r, final for this panel.
+// Entry (label i, label r) of the exchanged matrix is Y0[orig(i), orig(r)]:
+// one column of Y0 per step, read from its lower triangle (the trailing
+// matrix is kept as its lower triangle; rows above orig(r) read the mirrored
+// entry, negated).  The skr2k kernel applies the panel's permutation when it
+// forms the next trailing matrix.  The panel writes
 // nothing but its outputs: L, t, pivots, the permutation, the operands.
 // Other groups read the pivot row of L from a row-major mirror in HBM indexed
 // by register row, which is written once per column and never rewritten.
@@ -529,6 +530,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(
     // ---- panel start: carried column (column 0 of the panel) and the first
     //      column of Y
     double ycol = 0.0;
+    bool yneg = false; // ycol holds the negation of the entry (an upper one)
     for (int a = tid; a < NH; a += NT)
         hv[a] = 0.0;
     for (int a = tid; a < NA; a += NT)
@@ -620,7 +622,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(
             s = xor_add<32>(s);
         if constexpr (RL <= 16)
             s = xor_add<16>(s);
-        const double xv = ycol - s;
+        const double xv = (yneg ? -ycol : ycol) - s;
 
         // 3-4. group argmax, then (several groups) the exchange of the
         //      groups' candidates: every group arrives at the same pivot.
@@ -645,10 +647,11 @@ __global__ __launch_bounds__(NT) void panel_kernel(
         //       step's h) from the mirror, for thread a's h[a];
         //     - the next column: entry (label i, label r) of the exchanged
         //       matrix is Y0[orig(i), orig(r)], and orig(r) is the original
-        //       row of the register row that held p.  Every thread of a row
-        //       loads it (one address); rows that are final or absent load a
-        //       valid entry they do not use.  W is not written during the
-        //       panel.
+        //       row of the register row that held p; Y0 is kept as its lower
+        //       triangle, so rows above orig(r) read the mirrored entry and
+        //       negate it where it is used.  Every thread of a row loads it
+        //       (one address); rows that are final or absent load a valid
+        //       entry they do not use.  W is not written during the panel.
         //     Unused lanes read clamped addresses inside the same rows.
         const bool hthr = multi && tid <= j + 1 && j + 1 < nb;
         double mup = 0.0, mdn = 0.0;
@@ -657,7 +660,8 @@ __global__ __launch_bounds__(NT) void panel_kernel(
             mup = ld_dev(&mrow[hthr ? min(tid + 1, j + 1) : 0]);
             mdn = ld_dev(&mrow[(hthr && tid >= 1) ? tid - 1 : 0]);
         }
-        const double ynext = W[(size_t)(base + physp) * ldw + (exists ? orow : base)];
+        bool yneg_next;
+        const double ynext = W[skew_at(exists ? orow : base, base + physp, ldw, yneg_next)];
 
         // 5b. with one group the pivot row copies its L row to LDS (row p
         //     before the exchange); h is formed from it at the next step.
@@ -716,6 +720,7 @@ __global__ __launch_bounds__(NT) void panel_kernel(
                 hn += ((a - 1 == j) ? tau : tl[a - 1]) * mdn;
         }
         ycol = ynext;
+        yneg = yneg_next;
         if (multi && tid <= j + 1 && j + 1 < nb)
             hv[tid] = hn;
         if (tid == 0) {
@@ -899,7 +904,9 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
     // per lane and block of 16 slots, each slot's value broadcast inside the
     // 16-lane row as the FMA's DPP operand (slots of the unflushed group in
     // Lreg are 0)
-    auto gemv = [&](const double *h, double y) {
+    // (y is the loaded entry, ny whether it stands for its negation: the
+    // sign is applied here, where y is first used)
+    auto gemv = [&](const double *h, double y, bool ny) {
         const int hl = lane & 15;
         double hb[kNS / 16];
 #pragma unroll
@@ -926,10 +933,11 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
             sm = xor_add<32>(sm);
         if constexpr (RL <= 16)
             sm = xor_add<16>(sm);
-        return y - sm;
+        return (ny ? -y : y) - sm;
     };
 
     double ycol = 0.0;
+    bool yneg = false; // ycol holds the negation of the entry (an upper one)
     for (int a = tid; a < NA; a += NT) {
         hv[a] = 0.0;
         ho[a] = 0.0;
@@ -969,7 +977,7 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
         const int origC = (i == 0) ? k0 : base + wphys[2 * i - 1];
 
         // 1. x_c and the pivot
-        const double xv = gemv(hv, ycol);
+        const double xv = gemv(hv, ycol, yneg);
         // one group: its own mirror stores must be complete before the
         // barrier in the pivot search (several groups wait there anyway)
         if (!multi)
@@ -1015,9 +1023,13 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
         const double me0 = ld_dev(&mirror[(size_t)physE * ldm + ac]);
         const double me1 = ld_dev(&mirror[(size_t)physE * ldm + (ac ^ 1)]);
         const int yrow = exists ? orow : base;
-        const double yo = W[(size_t)(base + physp) * ldw + yrow];
-        const double wsc = W[(size_t)((a == 2 * i + 1) ? origC : base + physp) * ldw + base + physE];
-        const double ye = W[(size_t)(base + physE) * ldw + yrow];
+        // (Y0 is kept as its lower triangle: an upper entry is read at its
+        // mirror and negated where it is used)
+        bool yo_neg, wsc_neg, ye_neg;
+        const double yo = W[skew_at(yrow, base + physp, ldw, yo_neg)];
+        const double wsc =
+            W[skew_at(base + physE, (a == 2 * i + 1) ? origC : base + physp, ldw, wsc_neg)];
+        const double ye = W[skew_at(yrow, base + physE, ldw, ye_neg)];
 
         // 3a. l_i for the rows below r
         const bool below = exists && pos > r;
@@ -1047,7 +1059,7 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
         // 3b. the pair's second column and c_i
         // (rows that are not below r load a value they do not use: their xo
         // is discarded)
-        const double xo = gemv(ho, yo);
+        const double xo = gemv(ho, yo, yo_neg);
         insert(2 * i + 1, below ? xo : 0.0, below);
         mio.store(below && sub == (2 * i + 1) % TPR, phys, ldm, 2 * i + 1, xo);
 
@@ -1063,9 +1075,9 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
                     so += dred[1][q];
                 }
                 if (a == 2 * i) // -c_i[c+2]
-                    hn = -(wsc - so);
+                    hn = -((wsc_neg ? -wsc : wsc) - so);
                 else { // l_i[c+2]
-                    const double xk = wsc - sk;
+                    const double xk = (wsc_neg ? -wsc : wsc) - sk;
                     hn = (tau != 0.0) ? xk / tau : 0.0;
                 }
             }
@@ -1074,6 +1086,7 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
         // the next pair's candidates all have labels above c+2, for which
         // ye is their entry; the other rows' x is never used
         ycol = ye;
+        yneg = ye_neg;
         if (tid == 0) {
             tl[i] = tau;
             pl[i] = p;

@@ -3,7 +3,7 @@
 //
 // Sequence per call (paper arXiv 2411.09859, Sec. 3.6.3 fused blocked
 // right-looking algorithm with the pivoting of Sec. 3.7.3, code of Sec. 4.2):
-//   copy the input into full skew storage W0; for each panel of b columns:
+//   copy the input's lower triangle into W0; for each panel of b columns:
 //   panel kernel (pivot search, L columns, t, permutation, operands U and
 //   V; reads W only), then the skr2k kernel, which applies the panel's
 //   permutation and the update while writing the next trailing matrix into
@@ -43,7 +43,7 @@ int device_cu_count()
 // that columns do not sit at a power-of-two stride.
 static int work_ld(int n) { return ((n + 31) / 32) * 32 + 32; }
 
-// Workspace: two full skew work matrices (n x ldw fp64 each), the panel
+// Workspace: two work matrices (n x ldw fp64 each, the lower triangle used), the panel
 // permutation (n), mirror ((n + 512) x (b+2) fp64, row-major), carried
 // column (n), operands [U|V|-V|U] (n x 4k fp64) and their fp32 copy, slots,
 // gather maps.
@@ -188,7 +188,7 @@ static int factor_impl(int n, double *A, int lda, double *t, int *ipiv, int bloc
         if (n > 1 && (e = launch_fill_zero(ws.slots, kSlotArrayBytes, s)) !=
                          hipSuccess)
             return device_error(e, "clear slots");
-        if (n > 1 && (e = launch_init_full(A, lda, n, ws.W[0], ws.ldw, s)) != hipSuccess)
+        if (n > 1 && (e = launch_init_lower(A, lda, n, ws.W[0], ws.ldw, s)) != hipSuccess)
             return device_error(e, "full copy");
         tm_end(ti, s, 0.0);
     }
@@ -375,7 +375,7 @@ static int left_impl(int n, double *A, int lda, double *t, int *ipiv, int block_
         if (e == hipSuccess)
             e = launch_iota(ws.perm, n, s);
         if (e == hipSuccess && n > 1)
-            e = launch_init_full(A, lda, n, ws.W[0], ws.ldw, s);
+            e = launch_init_lower(A, lda, n, ws.W[0], ws.ldw, s);
         if (e != hipSuccess)
             return device_error(e, "left-looking set-up");
         tm_end(ti, s, 0.0);
@@ -477,7 +477,7 @@ extern "C" int skltlt_pfaffian_partial(int n, const double *A, int lda, double *
         if (n > 1 && (e = launch_fill_zero(ws.slots, kSlotArrayBytes, s)) !=
                          hipSuccess)
             return device_error(e, "clear slots");
-        if (n > 1 && (e = launch_init_full(A, lda, n, ws.W[0], ws.ldw, s)) != hipSuccess)
+        if (n > 1 && (e = launch_init_lower(A, lda, n, ws.W[0], ws.ldw, s)) != hipSuccess)
             return device_error(e, "full copy");
         tm_end(ti, s, 0.0);
     }

@@ -14,12 +14,13 @@
 // GEMM with K = 2k restricted to the strict lower triangle of the trailing
 // block (rows and columns cp..n-1, the first column included).
 //
-// The trailing matrix is held in full skew storage, and the panel does not
+// The trailing matrix is held as its lower triangle, and the panel does not
 // apply its row/column exchanges to it; this kernel does.  It reads
 // C[i][j] = Wc[perm[i]][perm[j]] (perm: row of the panel-start matrix that
-// position i holds after the panel's exchanges) and writes the updated entry
-// and its negation to (i, j) and (j, i) of the other buffer Wn, so each
-// panel's permutation costs no extra pass over the matrix.
+// position i holds after the panel's exchanges; an upper source entry is
+// read as the negation of its lower mirror) and writes the updated lower
+// entry (i, j) of the other buffer Wn, so each panel's permutation costs no
+// extra pass over the matrix.
 //
 // Tiling: a 128x128 output tile per 512-thread workgroup, eight waves of
 // 64x32 (64 rows, 32 columns), each a 4x2 grid of 16x16 MFMA blocks.  With
@@ -30,10 +31,9 @@
 // the largest update of n = 16384; eight of 64x32: 48).  The MFMA computes
 // the transposed tile, D[j][i], so that each lane's four accumulator values
 // lie in four columns at one row i and sixteen consecutive lanes cover
-// sixteen consecutive rows: loads of C and stores of the lower entries are
-// 128-byte segments, and the mirrored upper entries go out through an LDS
-// transpose as 256-byte column pieces; all C stores are streaming
-// (non-temporal): the next reader is the next panel or update, long after.
+// sixteen consecutive rows: loads of C and stores are 128-byte segments; all
+// C stores are streaming (non-temporal): the next reader is the next panel
+// or update, long after.
 // Tiles are enumerated over the lower triangle only; a diagonal tile skips
 // the waves whose 64x32 piece lies strictly above the diagonal and masks the
 // rest.
@@ -64,15 +64,10 @@ __device__ __forceinline__ void skr2k_tile(const double *__restrict__ Wc, double
     constexpr int BR = WR / 16, BC = WC / 16; // 16x16 blocks per wave tile
     constexpr int WPR = TMV / WR;             // waves along the rows
     static_assert(WPR * (TMV / WC) * 64 == NT, "waves cover the tile");
-    constexpr int TRS = WC + 2; // LDS row of the epilogue transpose (spreads banks)
-    // LDS: double-buffered operand chunks during the K loop, k-major, rows
-    // padded so that the four k-rows read by one fragment load fall in
-    // different LDS banks; afterwards each wave reuses 16 x TRS doubles of
-    // the same space to transpose its mirrored (upper) stores.
+    // LDS: double-buffered operand chunks, k-major, rows padded so that the
+    // four k-rows read by one fragment load fall in different LDS banks.
     constexpr size_t kOpBytes = sizeof(T) * 2 * KC * TMPV;
-    constexpr size_t kTrBytes = sizeof(double) * (NT / 64) * 16 * TRS;
-    constexpr size_t kLds = (2 * kOpBytes > kTrBytes) ? 2 * kOpBytes : kTrBytes;
-    __shared__ __attribute__((aligned(16))) char smem[kLds];
+    __shared__ __attribute__((aligned(16))) char smem[2 * kOpBytes];
     T(*sI)[KC][TMPV] = reinterpret_cast<T(*)[KC][TMPV]>(smem);            // [U|V] rows i
     T(*sJ)[KC][TMPV] = reinterpret_cast<T(*)[KC][TMPV]>(smem + kOpBytes); // [-V|U] rows j
     __shared__ int sPi[TMV], sPj[TMV]; // source rows of the tile's rows and columns
@@ -112,8 +107,12 @@ __device__ __forceinline__ void skr2k_tile(const double *__restrict__ Wc, double
         }
     }
     constexpr bool kF64 = sizeof(T) == 8;
-    auto csrc = [&](int gi, int gj) -> const double * {
-        return Wc + (size_t)sPj[gj - j0] * ldw + sPi[gi - i0];
+    // C[gi][gj] from the lower-triangle source (rows/columns past n have
+    // source row 0: still in range)
+    auto cval = [&](int gi, int gj) -> double {
+        bool neg;
+        const double v = Wc[skew_at(sPi[gi - i0], sPj[gj - j0], ldw, neg)];
+        return neg ? -v : v;
     };
 
     TileStage<T, NT, TMV, TMPV> tk(sI, sJ, uv, uv + (size_t)K * n, n, n, i0, j0, K);
@@ -132,8 +131,7 @@ __device__ __forceinline__ void skr2k_tile(const double *__restrict__ Wc, double
                 const int gj = jb + bj * 16 + MfmaT<T>::drow(lk, q);
                 T v = 0;
                 if (kF64) {
-                    // rows/columns past n have source row 0: still in range
-                    const double cv = *csrc(gi, gj);
+                    const double cv = cval(gi, gj);
                     v = (active && gi < n && gj < gi) ? (T)cv : (T)0;
                 }
                 acc[bi][bj][q] = v;
@@ -144,14 +142,8 @@ __device__ __forceinline__ void skr2k_tile(const double *__restrict__ Wc, double
     if (!active)
         return;
 
-    // D[m][nn] (m = MfmaT::drow(lane/16, q) : column j, nn = lane%16 : row i).
-    // Lower entries (i, j) go straight out: sixteen lanes write 128
-    // consecutive bytes of column j.  Their negations at (j, i) lie along
-    // column i, so each 16-row block is staged in this wave's LDS rows and
-    // written back one column i at a time: WC consecutive j per 64/WC of the
-    // wave, 64/WC columns i per store.
-    double *tr = reinterpret_cast<double *>(smem) + wave * 16 * TRS;
-    const int jl2 = lane % WC;
+    // D[m][nn] (m = MfmaT::drow(lane/16, q) : column j, nn = lane%16 : row i):
+    // sixteen lanes write 128 consecutive bytes of column j.
 #pragma unroll
     for (int bi = 0; bi < BR; ++bi) {
         const int gi = ib + bi * 16 + lrow;
@@ -159,33 +151,14 @@ __device__ __forceinline__ void skr2k_tile(const double *__restrict__ Wc, double
         for (int bj = 0; bj < BC; ++bj) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int jl = bj * 16 + MfmaT<T>::drow(lk, q);
-                const int gj = jb + jl;
-                double v = 0.0;
+                const int gj = jb + bj * 16 + MfmaT<T>::drow(lk, q);
                 if (gi < n && gj < gi) {
-                    v = kF64 ? (double)acc[bi][bj][q] : *csrc(gi, gj) + (double)acc[bi][bj][q];
+                    const double v =
+                        kF64 ? (double)acc[bi][bj][q] : cval(gi, gj) + (double)acc[bi][bj][q];
                     __builtin_nontemporal_store(v, &Wn[(size_t)gj * ldw + gi]);
                 }
-                tr[lrow * TRS + jl] = v;
             }
         }
-        // the wave's own LDS writes are visible to its later reads (LDS
-        // instructions of one wave execute in order)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int gj = jb + jl2;
-#pragma unroll
-        for (int r0 = 0; r0 < 16; r0 += 64 / WC) {
-            const int rr = r0 + lane / WC;
-            const int gi2 = ib + bi * 16 + rr;
-            const double v = tr[rr * TRS + jl2];
-            if (gi2 < n && gj < gi2)
-                __builtin_nontemporal_store(-v, &Wn[(size_t)gi2 * ldw + gj]);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
