@@ -9,7 +9,7 @@
 // Sec. 3.6.3); L and t are kept outside X while factoring and t is moved
 // onto the subdiagonal afterwards (Sec. 4.1).
 //
-// One cooperative launch handles one panel of nb column steps.  A workgroup
+// One launch handles one panel of nb column steps.  A workgroup
 // of 512 threads owns R = 512/TPR consecutive trailing rows; the TPR threads
 // of a row (64/TPR lanes apart in a wave) hold that row of the panel's L (the
 // carried column and the nb new ones, column a in thread a % TPR, register
@@ -47,6 +47,8 @@
 #include "wave_max.h"
 
 #include <climits>
+#include <cstdint>
+#include <mutex>
 
 namespace skl {
 
@@ -481,14 +483,15 @@ __global__ __launch_bounds__(NT) void panel_kernel(
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    // With one_xcd the grid holds 8 workgroups per panel group and only those
-    // with an id divisible by 8 work: workgroup ids are dealt round-robin to
-    // the 8 XCDs, so the working groups normally share one XCD; the kernel
-    // checks that (XCC_ID) before it lets the exchange use plain stores, so
-    // correctness does not depend on the placement, only the speed does.
+    // With one_xcd = 1 + x the grid holds 8 workgroups per panel group and
+    // only those whose id is x modulo 8 work: workgroup ids are dealt
+    // round-robin to the 8 XCDs, so the working groups normally share XCD x;
+    // the kernel checks that (XCC_ID) before it lets the exchange use plain
+    // stores, so correctness does not depend on the placement, only the speed
+    // does.
     int w = blockIdx.x;
     if (one_xcd) {
-        if (w & 7)
+        if ((w & 7) != one_xcd - 1)
             return;
         w >>= 3;
     }
@@ -851,9 +854,9 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    int w = blockIdx.x;
+    int w = blockIdx.x; // one_xcd: as in panel_kernel
     if (one_xcd) {
-        if (w & 7)
+        if ((w & 7) != one_xcd - 1)
             return;
         w >>= 3;
     }
@@ -1162,6 +1165,63 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
 //   b <= 256: TPR 4, 65 slots, 128 rows
 constexpr int kNT = 512;
 constexpr int kXcdCUs = 32; // CUs per XCD on MI355X
+
+// XCD that runs the ordinary one-XCD panel grids launched on stream s: the
+// first seven distinct streams seen get distinct XCDs among 1 .. 7 (later
+// ones the table's order modulo 7); XCD 0 is left to the cooperative one-XCD
+// grids.  Only a placement choice: the kernels check where their groups
+// landed.
+static int xcd_of_stream(hipStream_t s)
+{
+    constexpr int kTable = 64;
+    static std::mutex mu;
+    static hipStream_t seen[kTable];
+    static int nseen = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    for (int i = 0; i < nseen; ++i)
+        if (seen[i] == s)
+            return 1 + i % 7;
+    if (nseen < kTable) {
+        seen[nseen] = s;
+        return 1 + (nseen++) % 7;
+    }
+    return 1 + (int)(((uintptr_t)s >> 8) % 7);
+}
+
+// Launch of a panel grid of G working groups.  The working groups wait for
+// one another, so all of them must be resident together.
+// * G <= kOrdinaryGroups: an ordinary launch, its groups on the stream's XCD.
+//   The runtime serializes cooperative launches from all streams on one
+//   queue, so factorizations on several streams would otherwise run their
+//   panels one after another (measured on the serving mix: its n > 256
+//   requests on four streams 3.95 s with cooperative launches, 1.23 s with
+//   ordinary ones).  Residency holds by construction for up to seven
+//   streams: a stream's panels run one at a time on its own XCD (1 .. 7), at
+//   most 16 of its 32 CUs (one group per CU); a cooperative grid of up to 32
+//   groups runs on XCD 0, and one of 33 .. 128 groups needs at most 16 CUs
+//   of each XCD.  Beyond that (more streams, cooperative grids of more than
+//   128 groups at the same time) a group may have to wait for CUs held by
+//   waiting groups; the bounded waits then end the panel with a poisoned
+//   result (NaN t) instead of a hang.
+// * Larger grids: a cooperative launch (the runtime guarantees residency),
+//   placed on XCD 0 up to kXcdCUs groups.
+constexpr int kOrdinaryGroups = 16;
+static hipError_t launch_grid(const void *fn, int G, void **args, int *one_xcd, size_t lds,
+                              hipStream_t s)
+{
+    if (G == 1) { // no cross-group exchange
+        *one_xcd = 0;
+        return hipLaunchKernel(fn, dim3(1), dim3(kNT), args, (unsigned)lds, s);
+    }
+    if (G <= kOrdinaryGroups) {
+        *one_xcd = 1 + xcd_of_stream(s);
+        return hipLaunchKernel(fn, dim3(8 * G), dim3(kNT), args, (unsigned)lds, s);
+    }
+    *one_xcd = (G <= kXcdCUs) ? 1 : 0;
+    const int grid = *one_xcd ? 8 * G : G;
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kNT), args, (unsigned)lds, s);
+}
+
 static int shape_id(int b)
 {
     if (b + 1 <= 65)
@@ -1203,14 +1263,10 @@ static hipError_t launch_t(double *A, int lda, const double *W, int n, int k0, i
     float *uv32 = ws.uv32;
     Slot *slots = ws.slots;
     int G = sh.G;
-    int one_xcd = (G > 1 && G <= kXcdCUs) ? 1 : 0;
+    int one_xcd = 0; // set by launch_grid before the launch reads args
     void *args[] = {&A, &lda, &W, &ldw, &n, &k0, &nb, &b, &t, &ipiv, &perm, &mirror, &ldm,
                     &lcar, &uv, &uv32, &want32, &slots, &G, &one_xcd};
-    const void *fn = (const void *)panel_kernel<kNT, TPR, NS>;
-    if (G == 1) // no cross-group exchange: an ordinary launch
-        return hipLaunchKernel(fn, dim3(1), dim3(kNT), args, (unsigned)sh.lds, s);
-    const int grid = one_xcd ? 8 * G : G;
-    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kNT), args, (unsigned)sh.lds, s);
+    return launch_grid((const void *)panel_kernel<kNT, TPR, NS>, G, args, &one_xcd, sh.lds, s);
 }
 
 hipError_t launch_panel(double *A, int lda, const double *W, int n, int k0, int nb, int b,
@@ -1237,14 +1293,11 @@ static hipError_t launch_pair_t(const double *W, int n, int k0, int nb, double *
     float *uv32 = ws.uv32;
     Slot *slots = ws.slots;
     int G = sh.G;
-    int one_xcd = (G > 1 && G <= kXcdCUs) ? 1 : 0;
+    int one_xcd = 0; // set by launch_grid before the launch reads args
     void *args[] = {&W, &ldw, &n, &k0, &nb, &t, &ipiv, &perm, &mirror, &ldm,
                     &uv, &uv32, &want32, &slots, &G, &one_xcd};
-    const void *fn = (const void *)panel_pair_kernel<kNT, TPR, NS>;
-    if (G == 1)
-        return hipLaunchKernel(fn, dim3(1), dim3(kNT), args, (unsigned)sh.lds, s);
-    const int grid = one_xcd ? 8 * G : G;
-    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kNT), args, (unsigned)sh.lds, s);
+    return launch_grid((const void *)panel_pair_kernel<kNT, TPR, NS>, G, args, &one_xcd, sh.lds,
+                       s);
 }
 
 hipError_t launch_panel_pair(const double *W, int n, int k0, int nb, int b, double *t, int *ipiv,

@@ -11,8 +11,8 @@ overlaps their work on the GPU:
   variant asked for, and at these orders the update is a small share of the
   work); requests admitted while a batch runs join the next batch, which
   starts as soon as the batch stream is free;
-* the others run alone, spread over a pool of streams, in the precision
-  their tag asks for: a factorization request by ``skltlt_pfaffian`` (its
+* the others run alone, each on the stream of a pool with the least queued
+  work, in the precision their tag asks for: a factorization request by ``skltlt_pfaffian`` (its
   factors are handed back on the device), a Pfaffian request by
   ``skltlt_pfaffian_partial`` (half the pivot steps, nothing but the
   Pfaffian).
@@ -134,7 +134,10 @@ class FakeExecutor:
 class GpuExecutor:
     """Drives libskltlt on cuda:0: one batch stream, a pool of streams."""
 
-    def __init__(self, n_streams: int = 4, small_n: int = 256, device="cuda"):
+    def __init__(self, n_streams: int = 4, small_n: int = 256, device="cuda",
+                 policy: str = "least_loaded"):
+        if policy not in ("least_loaded", "round_robin"):
+            raise ValueError(f"unknown stream policy {policy!r}")
         import torch
         from . import binding
         self.torch = torch
@@ -143,8 +146,28 @@ class GpuExecutor:
         self.small_n = small_n
         self.batch_stream = torch.cuda.Stream(device=device)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        self.policy = policy
         self.next_stream = 0
+        # work queued on each stream and not yet seen complete, in units of
+        # the order n (a single request's time grows about linearly with n at
+        # these orders: its column steps)
+        self.load = [0] * n_streams
         self.inflight = []  # (event, payload)
+
+    def _pick_stream(self, n):
+        """Round robin, or the stream with the least queued work (ties go to
+        the next stream in round-robin order, so an idle pool is used in
+        turn).  Under load, round robin queues a long request ahead of short
+        ones on one stream while another idles."""
+        ns = len(self.streams)
+        if self.policy == "round_robin":
+            k = self.next_stream
+        else:
+            order = [(self.next_stream + i) % ns for i in range(ns)]
+            k = min(order, key=lambda q: self.load[q])
+        self.next_stream = (k + 1) % ns
+        self.load[k] += n
+        return k
 
     def nbytes(self, req):
         return request_bytes(req.n, req.precision)
@@ -176,11 +199,20 @@ class GpuExecutor:
             ns = [r.n for r in reqs]
             ts = [torch.empty(max(n - 1, 1), dtype=torch.float64, device=self.device) for n in ns]
             ps = [torch.empty(max(n, 1), dtype=torch.int32, device=self.device) for n in ns]
-            n_dev = torch.tensor(ns, dtype=torch.int32, device=self.device)
-            lda = torch.tensor([max(n, 1) for n in ns], dtype=torch.int32, device=self.device)
-            A_ptr = torch.tensor([m.data_ptr() for m in mats], dtype=torch.int64, device=self.device)
-            t_ptr = torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64, device=self.device)
-            p_ptr = torch.tensor([p.data_ptr() for p in ps], dtype=torch.int64, device=self.device)
+            # the descriptor arrays go up in one asynchronous copy from pinned
+            # memory (a device tensor built from a Python list is a blocking
+            # pageable copy that waits for the GPU)
+            k = len(reqs)
+            desc_h = torch.empty(5 * k, dtype=torch.int64, pin_memory=True)
+            desc_h[0:k] = torch.tensor(ns, dtype=torch.int64)
+            desc_h[k:2 * k] = torch.tensor([max(n, 1) for n in ns], dtype=torch.int64)
+            desc_h[2 * k:3 * k] = torch.tensor([m.data_ptr() for m in mats], dtype=torch.int64)
+            desc_h[3 * k:4 * k] = torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64)
+            desc_h[4 * k:5 * k] = torch.tensor([p.data_ptr() for p in ps], dtype=torch.int64)
+            desc = desc_h.to(self.device, non_blocking=True)
+            n_dev = desc[0:k].to(torch.int32)
+            lda = desc[k:2 * k].to(torch.int32)
+            A_ptr, t_ptr, p_ptr = desc[2 * k:3 * k], desc[3 * k:4 * k], desc[4 * k:5 * k]
             la = torch.empty(len(reqs), dtype=torch.float64, device=self.device)
             sg = torch.empty(len(reqs), dtype=torch.int32, device=self.device)
             info = torch.empty(len(reqs), dtype=torch.int32, device=self.device)
@@ -195,14 +227,14 @@ class GpuExecutor:
             in_h.copy_(info, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        keep = (mats, ts, ps, n_dev, lda, A_ptr, t_ptr, p_ptr, la, sg, info, work)
+        keep = (mats, ts, ps, desc_h, desc, n_dev, lda, A_ptr, t_ptr, p_ptr, la, sg, info, work)
         facs = [(mats[k], ts[k], ps[k]) if r.factor else None for k, r in enumerate(reqs)]
         self.inflight.append((ev, ("batched", reqs, la_h, sg_h, keep, facs, in_h)))
 
     def launch_single(self, req):
         torch, binding = self.torch, self.binding
-        s = self.streams[self.next_stream]
-        self.next_stream = (self.next_stream + 1) % len(self.streams)
+        k = self._pick_stream(req.n)
+        s = self.streams[k]
         with torch.cuda.stream(s):
             A = self._materialize(req, s)
             n = req.n
@@ -224,7 +256,7 @@ class GpuExecutor:
             ev.record(s)
         path = "single" if req.factor else "partial"
         facs = [(A, t, ip)] if req.factor else [None]
-        self.inflight.append((ev, (path, [req], la_h, sg_h, (A, t, ip, la, sg, work), facs,
+        self.inflight.append((ev, (path, [req], la_h, sg_h, (A, t, ip, la, sg, work, k), facs,
                                    None)))
 
     def batch_busy(self):
@@ -235,6 +267,8 @@ class GpuExecutor:
         for ev, payload in self.inflight:
             if ev.query():
                 path, reqs, la_h, sg_h, bufs, facs, in_h = payload
+                if path != "batched":
+                    self.load[bufs[-1]] -= reqs[0].n
                 for k, r in enumerate(reqs):
                     err = None
                     if in_h is not None and int(in_h[k]) != 0:

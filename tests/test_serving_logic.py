@@ -121,3 +121,32 @@ def test_fake_executor_with_oracle_pfaffians():
     for r in srv.results:
         la, sg = pf(reqs[r.rid])
         assert r.log_abs_pf == la and r.sign == sg
+
+
+def test_gpu_executor_stream_choice():
+    """The executor's stream choice (host logic only: no stream is created):
+    least queued work first, ties in round-robin order; round robin rotates
+    whatever the load."""
+    from paper_2411_09859_amd.serving import GpuExecutor
+
+    def bare(policy):
+        ex = object.__new__(GpuExecutor)
+        ex.streams = [None] * 4
+        ex.policy = policy
+        ex.next_stream = 0
+        ex.load = [0] * 4
+        return ex
+
+    ex = bare("least_loaded")
+    assert [ex._pick_stream(100) for _ in range(4)] == [0, 1, 2, 3]  # idle pool: in turn
+    ex.load[0] -= 100                       # stream 0's request completed
+    assert ex._pick_stream(2000) == 0
+    assert ex._pick_stream(50) == 1          # 1, 2, 3 tie at 100: next in turn
+    ex.load = [2000, 150, 100, 100]
+    ex.next_stream = 3
+    assert ex._pick_stream(10) == 3 and ex._pick_stream(10) == 2
+    rr = bare("round_robin")
+    rr.load = [0, 10 ** 6, 0, 0]
+    assert [rr._pick_stream(1) for _ in range(6)] == [0, 1, 2, 3, 0, 1]
+    with pytest.raises(ValueError):
+        GpuExecutor.__init__(object.__new__(GpuExecutor), policy="random")
