@@ -39,6 +39,16 @@
  *     Inputs with NaN or Inf are outside the contract (as in LAPACK).
  *   - Calls on distinct streams with distinct buffers are independent; two
  *     calls may not share a workspace while both are in flight.
+ *   - Concurrency: the panel kernels' workgroups wait for one another and
+ *     must be resident together.  Panels of at most 16 workgroups (matrices
+ *     up to order 2049 at panel width 256, the last panels of larger ones)
+ *     are ordinary launches, so factorizations on different streams overlap;
+ *     each of the first seven streams a process uses gets its own XCD for
+ *     them.  Larger panels are cooperative launches, which the runtime runs
+ *     one at a time across streams.  Up to seven streams factoring at once
+ *     are guaranteed to make progress; beyond that a starved panel ends
+ *     after its bounded waits with NaN in t (and the Pfaffian) rather than
+ *     hanging.
  */
 #ifndef SKLTLT_H
 #define SKLTLT_H
