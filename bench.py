@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+
 PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 MFMA
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 MFMA
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
@@ -369,6 +370,7 @@ def bench_serving(torch, count, short_count, seed=5, deadline=None):
     log(f"[bench] serving closed loop {closed}")
     out = {"workload": f"n log-uniform even in [32,2048], FP64/FP32-update 50/50, "
                        f"factorization/Pfaffian 50/50, Poisson arrivals, 64 GB budget",
+           "single_request_streams": 4,
            "closed_loop": closed}
     for pct, sd, want in ((80, seed + 1, count), (50, seed + 2, short_count),
                           (95, seed + 3, short_count)):

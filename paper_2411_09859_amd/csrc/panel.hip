@@ -976,7 +976,9 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
         const unsigned stamp = (unsigned)((c >> 1) + 1);
         // window labels: r = base + 2i, c+2 = base + 2i + 1, c = base + 2i - 1
         const int physR0 = wphys[2 * i];
-        const int physE0 = (2 * i + 1 < nb) ? wphys[2 * i + 1] : 0;
+        // label c+2 is n (no row) at the last pair of a panel that ends the
+        // matrix: its loads then read an existing row and are discarded
+        const int physE0 = (2 * i + 1 < nb && base + 2 * i + 1 < n) ? wphys[2 * i + 1] : 0;
         const int origC = (i == 0) ? k0 : base + wphys[2 * i - 1];
 
         // 1. x_c and the pivot
@@ -1012,11 +1014,11 @@ __global__ __launch_bounds__(NT) void panel_pair_kernel(
         const bool ha = (a < 2 * i);
         // Every thread issues every load of the pair, in the order of their
         // use, at addresses kept in range (rows and columns named by the
-        // window always exist); what a thread does not need is discarded
-        // where the value is used.  A load issued on some paths only makes
-        // the compiler's waits for the earlier ones also cover the later
-        // ones: the next column's HBM load then sat before the pair's
-        // barriers.  Order: the pivot row's and the label-(c+2) row's mirror
+        // window exist, label n excepted: see physE0); what a thread does
+        // not need is discarded where the value is used.  A load issued on
+        // some paths only makes the compiler's waits for the earlier ones
+        // also cover the later ones: the next column's HBM load then sat
+        // before the pair's barriers.  Order: the pivot row's and the label-(c+2) row's mirror
         // entries (for h of the second column and the dot products), the
         // second column (every thread of a row loads, one address), entries
         // (label c+2, label r) or (label c+2, label c) of Y, and last the

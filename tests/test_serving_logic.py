@@ -150,3 +150,4 @@ def test_gpu_executor_stream_choice():
     assert [rr._pick_stream(1) for _ in range(6)] == [0, 1, 2, 3, 0, 1]
     with pytest.raises(ValueError):
         GpuExecutor.__init__(object.__new__(GpuExecutor), policy="random")
+
